@@ -1,0 +1,400 @@
+"""FP64 oracle of the T2-Shuffling per-slice reconstruction (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and ``bench.py``'s ``cpu_baseline`` leg, never by the product path.
+
+Everything here is plain NumPy in complex128 / float64, written to be read
+against the paper (Anderson, Tamir et al., "T2 Shuffling ... distributed
+reconstruction", arXiv 1809.04195):
+
+* forward model of one readout slice, Sec. II-A eq. (coilmodel) with the
+  temporal subspace of Sec. II-B eq. (backproj): y = P F S Phi alpha;
+* problem solved, Sec. II-B eq. (t2shpics): 1/2 ||y - P F S Phi alpha||^2
+  + lambda * sum_blocks ||R(alpha)||_* ;
+* space-time kernel Psi(n) = Phi^T P(n) Phi of Sec. IV-B (real, symmetric);
+* non-overlapping LLR blocks under a random circular shift each iteration,
+  Sec. II-B (end) and the single-pass variant of Sec. IV-C;
+* ADMM (scaled form) with a CG inner solve on A^H A + rho I.  The paper itself
+  runs FISTA (Sec. II-A); ``fista`` is provided for cross-checking objectives.
+
+Array conventions (shared with the C ABI, as plain data):
+  alpha        complex [K, Ny, Nz]          subspace coefficient images
+  sens         complex [C, Ny, Nz]          coil maps S_c (M = 1 map set)
+  phi          real    [T, K]               temporal basis
+  masks        bool    [T, Ny, Nz]          centred sampling masks, DC at (Ny/2, Nz/2)
+  samples      complex [C, P_tot]           measured k-space in *mask order*:
+                                            echo-major, then row-major (y, z)
+                                            position inside mask_t.
+Frequency index j of a mask / k-space array means frequency j - N/2 (centred).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Centred unitary 2D DFT  (Sec. II-A: F is the 2D DFT; the pipeline uses unitary
+# transforms on centred data, Sec. III-B and the FFTmod step of Sec. IV-A)
+# ---------------------------------------------------------------------------
+
+
+def fft2c(x: np.ndarray) -> np.ndarray:
+    """Centred orthonormal 2D DFT over the last two axes.
+
+    (F x)[j] = N^{-1/2} sum_i x[i] exp(-2 pi i (j - N/2)(i - N/2) / N) per axis,
+    which for even N equals fftshift(fft2(ifftshift(x))) / sqrt(N).
+    """
+    ax = (-2, -1)
+    return np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(x, axes=ax), axes=ax, norm="ortho"), axes=ax)
+
+
+def ifft2c(X: np.ndarray) -> np.ndarray:
+    """Adjoint (= inverse) of ``fft2c``."""
+    ax = (-2, -1)
+    return np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(X, axes=ax), axes=ax, norm="ortho"), axes=ax)
+
+
+# ---------------------------------------------------------------------------
+# Sampling pattern in truncated form (Sec. II-A: P in {0,1}^{P x N})
+# ---------------------------------------------------------------------------
+
+
+def mask_order(masks: np.ndarray):
+    """Return (echo index, flat location) of every sample, in mask order.
+
+    Mask order is echo-major, then row-major (y, z) location inside mask_t.
+    """
+    masks = np.asarray(masks).astype(bool)
+    T = masks.shape[0]
+    t_idx, loc = [], []
+    for t in range(T):
+        flat = np.flatnonzero(masks[t].reshape(-1))
+        t_idx.append(np.full(flat.size, t, dtype=np.int64))
+        loc.append(flat)
+    return np.concatenate(t_idx), np.concatenate(loc)
+
+
+# ---------------------------------------------------------------------------
+# Forward and adjoint operators  (eq. coilmodel + eq. backproj, i.e. A = P F S Phi)
+# ---------------------------------------------------------------------------
+
+
+def forward(alpha, sens, phi, masks):
+    """A alpha: samples[c, p] = (F(S_c x_t))[loc_p] with x_t = sum_k Phi[t,k] alpha_k, t = t_p."""
+    alpha = np.asarray(alpha, dtype=np.complex128)
+    sens = np.asarray(sens, dtype=np.complex128)
+    phi = np.asarray(phi, dtype=np.float64)
+    T = phi.shape[0]
+    C, Ny, Nz = sens.shape
+    t_of, loc = mask_order(masks)
+    x = np.einsum("tk,kyz->tyz", phi, alpha)                    # back-projection to echoes
+    out = np.empty((C, t_of.size), dtype=np.complex128)
+    for c in range(C):
+        kspace = fft2c(sens[c][None] * x).reshape(T, Ny * Nz)   # [T, N] full k-space
+        out[c] = kspace[t_of, loc]                              # P: keep sampled entries
+    return out
+
+
+def adjoint(samples, sens, phi, masks):
+    """A^H y: zero-fill each echo, project onto the basis, inverse DFT, coil-combine."""
+    samples = np.asarray(samples, dtype=np.complex128)
+    sens = np.asarray(sens, dtype=np.complex128)
+    phi = np.asarray(phi, dtype=np.float64)
+    T, K = phi.shape
+    C, Ny, Nz = sens.shape
+    t_of, loc = mask_order(masks)
+    alpha = np.zeros((K, Ny, Nz), dtype=np.complex128)
+    for c in range(C):
+        full = np.zeros((T, Ny * Nz), dtype=np.complex128)
+        full[t_of, loc] = samples[c]                            # P^H: zero-fill
+        proj = np.einsum("tk,tn->kn", phi, full).reshape(K, Ny, Nz)   # Phi^T
+        alpha += np.conj(sens[c])[None] * ifft2c(proj)          # S^H F^H
+    return alpha
+
+
+# ---------------------------------------------------------------------------
+# Space-time kernel and the normal operator (Sec. IV-B, eqs. commute / normaleq)
+# ---------------------------------------------------------------------------
+
+
+def space_time_kernel(phi, masks):
+    """Psi(n) = Phi^T P(n) Phi = sum_{t : m_t(n)=1} phi_t^T phi_t, shape [K, K, Ny, Nz] (real)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    m = np.asarray(masks).astype(np.float64)
+    return np.einsum("tk,tl,tyz->klyz", phi, phi, m)
+
+
+def normal_explicit(alpha, sens, phi, masks):
+    """Route (i): A^H (A alpha)."""
+    return adjoint(forward(alpha, sens, phi, masks), sens, phi, masks)
+
+
+def normal_psi(alpha, sens, psi):
+    """Route (ii): N(alpha)_k = sum_c conj(S_c) F^H( sum_l Psi_kl F(S_c alpha_l) )."""
+    alpha = np.asarray(alpha, dtype=np.complex128)
+    sens = np.asarray(sens, dtype=np.complex128)
+    out = np.zeros_like(alpha)
+    for c in range(sens.shape[0]):
+        ks = fft2c(sens[c][None] * alpha)                       # [K, Ny, Nz]
+        mixed = np.einsum("klyz,lyz->kyz", psi, ks)
+        out += np.conj(sens[c])[None] * ifft2c(mixed)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Locally-low-rank proximal map  (eq. llr; random shift + non-overlapping b x b
+# blocks, Sec. II-B; single pass over the images, Sec. IV-C)
+# ---------------------------------------------------------------------------
+
+
+def svt(X: np.ndarray, tau: float) -> np.ndarray:
+    """Singular-value soft threshold of a matrix: U diag(max(s - tau, 0)) V^H."""
+    U, s, Vh = np.linalg.svd(X, full_matrices=False)
+    return (U * np.maximum(s - tau, 0.0)) @ Vh
+
+
+def llr_prox(v, tau, shift, b):
+    """Single-pass LLR prox: gather each shifted block, threshold, scatter back.
+
+    Block (p, q) holds rows (p*b + i + s_y) mod Ny and columns (q*b + j + s_z) mod Nz,
+    i, j in [0, b); its B x K matrix has one row per voxel (row-major inside the
+    block) and one column per coefficient image.  Ny and Nz must be multiples of b.
+    """
+    v = np.asarray(v, dtype=np.complex128)
+    K, Ny, Nz = v.shape
+    sy, sz = shift
+    if Ny % b or Nz % b:
+        raise ValueError("grid must be a multiple of the block size")
+    out = np.empty_like(v)
+    for p in range(Ny // b):
+        rows = (p * b + np.arange(b) + sy) % Ny
+        for q in range(Nz // b):
+            cols = (q * b + np.arange(b) + sz) % Nz
+            blk = v[:, rows[:, None], cols[None, :]]           # [K, b, b]
+            X = blk.reshape(K, b * b).T                         # [B, K]
+            out[:, rows[:, None], cols[None, :]] = svt(X, tau).T.reshape(K, b, b)
+    return out
+
+
+def llr_prox_explicit(v, tau, shift, b):
+    """The same prox written as: circular shift, extract non-overlapping blocks,
+    threshold, reassemble, shift back (the multi-pass form the paper replaced)."""
+    v = np.asarray(v, dtype=np.complex128)
+    K, Ny, Nz = v.shape
+    sy, sz = shift
+    w = np.roll(v, (-sy, -sz), axis=(1, 2))                     # w[i] = v[i + s]
+    blocks = w.reshape(K, Ny // b, b, Nz // b, b).transpose(1, 3, 2, 4, 0).reshape(Ny // b, Nz // b, b * b, K)
+    res = np.empty_like(blocks)
+    for p in range(Ny // b):
+        for q in range(Nz // b):
+            res[p, q] = svt(blocks[p, q], tau)
+    w2 = res.reshape(Ny // b, Nz // b, b, b, K).transpose(4, 0, 2, 1, 3).reshape(K, Ny, Nz)
+    return np.roll(w2, (sy, sz), axis=(1, 2))
+
+
+def llr_value(alpha, shift, b):
+    """sum over the shifted non-overlapping blocks of the nuclear norm (eq. llr, blocked form)."""
+    alpha = np.asarray(alpha, dtype=np.complex128)
+    K, Ny, Nz = alpha.shape
+    sy, sz = shift
+    total = 0.0
+    for p in range(Ny // b):
+        rows = (p * b + np.arange(b) + sy) % Ny
+        for q in range(Nz // b):
+            cols = (q * b + np.arange(b) + sz) % Nz
+            X = alpha[:, rows[:, None], cols[None, :]].reshape(K, b * b).T
+            total += np.linalg.svd(X, compute_uv=False).sum()
+    return total
+
+
+def objective(alpha, samples, sens, phi, masks, lam, shift, b):
+    """Value of eq. (t2shpics) with the blocked regulariser at a fixed shift."""
+    res = samples - forward(alpha, sens, phi, masks)
+    return 0.5 * np.vdot(res, res).real + lam * llr_value(alpha, shift, b)
+
+
+# ---------------------------------------------------------------------------
+# Random block shift: SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), counter based
+# ---------------------------------------------------------------------------
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """One SplitMix64 output for state x (state advanced by the golden gamma first)."""
+    z = (x + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def block_shift(seed: int, g: int, k: int, b: int):
+    """Shift (s_y, s_z) in [0, b)^2 of global slice g at outer iteration k.
+
+    h = sm(sm(sm(seed) xor g) xor k); s_y = (h mod 2^32) mod b; s_z = (h >> 32) mod b.
+    """
+    h = splitmix64(splitmix64(splitmix64(seed & _M64) ^ (g & _M64)) ^ (k & _M64))
+    return (h & 0xFFFFFFFF) % b, (h >> 32) % b
+
+
+# ---------------------------------------------------------------------------
+# Conjugate gradient on M = A^H A + rho I
+# ---------------------------------------------------------------------------
+
+
+def cg(apply_m, x0, rhs, n_iter):
+    """Plain CG (no preconditioner), warm-started at x0, explicit initial residual.
+
+    <u, v> = sum conj(u) v; the step uses Re<p, Mp>.  Stops early if gamma == 0.
+    """
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    r = rhs - apply_m(x)
+    p = r.copy()
+    gamma = np.vdot(r, r).real
+    for _ in range(n_iter):
+        if gamma == 0.0:
+            break
+        w = apply_m(p)
+        pw = np.vdot(p, w).real
+        if pw == 0.0:
+            break
+        a = gamma / pw
+        x += a * p
+        r -= a * w
+        gamma_new = np.vdot(r, r).real
+        p = r + (gamma_new / gamma) * p
+        gamma = gamma_new
+    return x
+
+
+# ---------------------------------------------------------------------------
+# ADMM (scaled form; Boyd et al. 2011, Sec. 3.1.1) for eq. (t2shpics)
+# ---------------------------------------------------------------------------
+
+
+class AdmmResult:
+    def __init__(self, alpha, z, u, history, k_freeze, n_outer):
+        self.alpha = alpha
+        self.z = z
+        self.u = u
+        self.history = history          # list of dicts, one per outer iteration
+        self.k_freeze = k_freeze        # outer index whose shift was frozen (-1: never)
+        self.n_outer = n_outer          # outer iterations run
+
+
+def admm_residuals(alpha, z, z_prev, u, rho):
+    """Relative primal residual ||alpha - z|| / max(||alpha||, ||z||) and dual
+    residual rho ||z - z_prev|| / ||rho u|| (+inf while u = 0)."""
+    na, nz = np.linalg.norm(alpha), np.linalg.norm(z)
+    den = max(na, nz)
+    rp = np.linalg.norm(alpha - z) / den if den > 0 else 0.0
+    nu = np.linalg.norm(rho * u)
+    rd = rho * np.linalg.norm(z - z_prev) / nu if nu > 0 else np.inf
+    return rp, rd
+
+
+def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
+         alpha0=None, tol=0.0, freeze_window=5, freeze_stall=0.05, check_every=5,
+         fixed_shift=None, replay=None, normal="psi"):
+    """Solve eq. (t2shpics) for one slice.
+
+    Per outer iteration k:
+      1. alpha <- CG(alpha, b0 + rho (z - u), n_cg) on M = A^H A + rho I
+      2. z <- LLR prox with threshold lam/rho at shift(seed, g, k) (or the frozen shift)
+      3. u <- u + alpha - z
+    Fixed mode (tol == 0): exactly n_outer iterations, a new shift every iteration.
+    Tolerance mode (tol > 0): decisions are taken after outer iterations k with
+    (k + 1) % check_every == 0, in this order: stop if the shift was already frozen
+    and max(r_p, r_d) <= tol; else freeze at shift k if max(r_p, r_d) at k exceeds
+    (1 - freeze_stall) times its value at k - freeze_window.  n_outer is the cap.
+    ``replay`` = (k_freeze, n_run) imposes another run's decisions instead.
+    """
+    sens = np.asarray(sens, dtype=np.complex128)
+    phi = np.asarray(phi, dtype=np.float64)
+    K = phi.shape[1]
+    C, Ny, Nz = sens.shape
+    tau = lam / rho
+    b0 = adjoint(samples, sens, phi, masks)
+    if normal == "psi":
+        psi = space_time_kernel(phi, masks)
+
+        def apply_m(v):
+            return normal_psi(v, sens, psi) + rho * v
+    else:
+        def apply_m(v):
+            return normal_explicit(v, sens, phi, masks) + rho * v
+
+    if alpha0 is None:
+        alpha = np.zeros((K, Ny, Nz), dtype=np.complex128)
+    else:
+        alpha = np.array(alpha0, dtype=np.complex128, copy=True)
+    z = alpha.copy()
+    u = np.zeros_like(alpha)
+    history = []
+    k_freeze = -1
+    k = 0
+    while k < n_outer:
+        alpha = cg(apply_m, alpha, b0 + rho * (z - u), n_cg)
+        z_prev = z
+        if fixed_shift is not None:
+            shift = fixed_shift
+        elif k_freeze >= 0:
+            shift = block_shift(seed, g, k_freeze, b)
+        else:
+            shift = block_shift(seed, g, k, b)
+        z = llr_prox(alpha + u, tau, shift, b)
+        u = u + alpha - z
+        rp, rd = admm_residuals(alpha, z, z_prev, u, rho)
+        history.append(dict(k=k, shift=shift, r_primal=rp, r_dual=rd, res=max(rp, rd)))
+        k += 1
+        if replay is not None:
+            rk_freeze, rn = replay
+            if rk_freeze >= 0 and k - 1 == rk_freeze:
+                k_freeze = rk_freeze
+            if k >= rn:
+                break
+            continue
+        if tol > 0 and k % check_every == 0:
+            res = history[-1]["res"]
+            if k_freeze >= 0 and res <= tol:
+                break
+            if k_freeze < 0 and k - 1 >= freeze_window:
+                if res > (1.0 - freeze_stall) * history[k - 1 - freeze_window]["res"]:
+                    k_freeze = k - 1
+    return AdmmResult(alpha, z, u, history, k_freeze, k)
+
+
+# ---------------------------------------------------------------------------
+# FISTA (the paper's solver, Sec. II-A) at a fixed block shift, for cross-checks
+# ---------------------------------------------------------------------------
+
+
+def fista(samples, sens, phi, masks, lam, b, n_iter, shift, step=None):
+    """Proximal gradient with Nesterov momentum (Beck & Teboulle 2009) on eq. (t2shpics).
+
+    The gradient is A^H A x - A^H y; the step is 1/L with L the largest eigenvalue of
+    A^H A (estimated by power iteration when not given).
+    """
+    sens = np.asarray(sens, dtype=np.complex128)
+    phi = np.asarray(phi, dtype=np.float64)
+    K = phi.shape[1]
+    C, Ny, Nz = sens.shape
+    psi = space_time_kernel(phi, masks)
+    aty = adjoint(samples, sens, phi, masks)
+    if step is None:
+        v = np.random.default_rng(1).standard_normal((K, Ny, Nz)) + 0j
+        for _ in range(100):
+            v = normal_psi(v, sens, psi)
+            v /= np.linalg.norm(v)
+        L = np.vdot(v, normal_psi(v, sens, psi)).real
+        step = 1.0 / L
+    x = np.zeros((K, Ny, Nz), dtype=np.complex128)
+    yk = x.copy()
+    t = 1.0
+    for _ in range(n_iter):
+        grad = normal_psi(yk, sens, psi) - aty
+        x_new = llr_prox(yk - step * grad, lam * step, shift, b)
+        t_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
+        yk = x_new + ((t - 1.0) / t_new) * (x_new - x)
+        x, t = x_new, t_new
+    return x

@@ -1,0 +1,354 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test targets one oracle function and is chosen so that a plausible mistake
+(a dropped term, a wrong sign or index, a transposed operand) fails it.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import t2s as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def crandn(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def small_problem(rng, ny=16, nz=24, C=3, T=6, K=3, frac=0.3):
+    phi, _ = np.linalg.qr(rng.standard_normal((T, K)))
+    sens = crandn(rng, C, ny, nz)
+    sens /= np.sqrt((np.abs(sens) ** 2).sum(0))[None]
+    masks = rng.random((T, ny, nz)) < frac
+    return phi, sens, masks
+
+
+# --- T1: centred DFT against the direct DFT matrix of its definition -------------------
+
+
+def dft_matrix(n):
+    j = np.arange(n)[:, None] - n // 2
+    i = np.arange(n)[None, :] - n // 2
+    return np.exp(-2j * np.pi * j * i / n) / np.sqrt(n)
+
+
+@pytest.mark.parametrize("ny,nz", [(4, 4), (6, 10), (12, 8), (12, 20), (24, 40), (10, 6)])
+def test_fft2c_matches_direct_dft(ny, nz):
+    rng = np.random.default_rng(ny * 100 + nz)
+    x = crandn(rng, 2, ny, nz)
+    Dy, Dz = dft_matrix(ny), dft_matrix(nz)
+    # brute force double sum for one image, matrix form for the other
+    X0 = np.zeros((ny, nz), dtype=complex)
+    for jy in range(ny):
+        for jz in range(nz):
+            X0[jy, jz] = np.sum(Dy[jy][:, None] * Dz[jz][None, :] * x[0])
+    assert rel(O.fft2c(x)[0], X0) < 1e-12
+    assert rel(O.fft2c(x)[1], Dy @ x[1] @ Dz.T) < 1e-12
+    assert rel(O.ifft2c(O.fft2c(x)), x) < 1e-12
+    assert rel(O.ifft2c(x)[1], Dy.conj().T @ x[1] @ Dz.conj()) < 1e-12
+
+
+# --- T2: centring by +-1 modulation (FFTmod, Sec. IV-A) and the shifted kernel -------------
+
+
+@pytest.mark.parametrize("ny,nz", [(8, 8), (6, 10), (16, 12)])
+def test_centring_is_sign_modulation(ny, nz):
+    rng = np.random.default_rng(3)
+    x = crandn(rng, ny, nz)
+    sgn = (-1.0) ** (np.arange(ny)[:, None] + np.arange(nz)[None, :])
+    const = (-1.0) ** ((ny + nz) // 2)
+    ref = const * sgn * np.fft.fft2(sgn * x) / np.sqrt(ny * nz)
+    assert rel(O.fft2c(x), ref) < 1e-12
+
+
+def test_shifted_kernel_removes_centring():
+    # F^H diag(psi) F x == IFFT0( ifftshift(psi) * FFT0(x) ) with plain (uncentred) transforms
+    rng = np.random.default_rng(4)
+    ny, nz = 12, 16
+    x = crandn(rng, ny, nz)
+    psi = rng.standard_normal((ny, nz))
+    lhs = O.ifft2c(psi * O.fft2c(x))
+    rhs = np.fft.ifft2(np.fft.ifftshift(psi) * np.fft.fft2(x))
+    assert rel(lhs, rhs) < 1e-12
+
+
+# --- T3: adjoint identity --------------------------------------------------------------------
+
+
+def test_adjoint_identity():
+    rng = np.random.default_rng(5)
+    phi, sens, masks = small_problem(rng)
+    K = phi.shape[1]
+    a = crandn(rng, K, *sens.shape[1:])
+    y = crandn(rng, sens.shape[0], int(masks.sum()))
+    lhs = np.vdot(y, O.forward(a, sens, phi, masks))          # <y, A a>
+    rhs = np.vdot(O.adjoint(y, sens, phi, masks), a)          # <A^H y, a>
+    assert abs(lhs - rhs) / abs(lhs) < 1e-12
+
+
+def test_forward_samples_in_mask_order():
+    # one nonzero coefficient image, one coil of ones, one echo: samples are F(alpha)[mask] row-major
+    rng = np.random.default_rng(6)
+    ny, nz, T, K = 8, 8, 2, 1
+    phi = np.array([[2.0], [-1.0]])
+    sens = np.ones((1, ny, nz), dtype=complex)
+    masks = np.zeros((T, ny, nz), dtype=bool)
+    masks[0, 1, 5] = masks[0, 3, 2] = True
+    masks[1, 0, 0] = True
+    a = crandn(rng, K, ny, nz)
+    Fa = O.fft2c(a[0])
+    y = O.forward(a, sens, phi, masks)[0]
+    assert np.allclose(y, [2 * Fa[1, 5], 2 * Fa[3, 2], -Fa[0, 0]], rtol=1e-13)
+
+
+# --- T4: the subspace commutes with coils and Fourier transform (Sec. IV-B) ---------------
+
+
+def test_commute():
+    rng = np.random.default_rng(7)
+    phi, sens, _ = small_problem(rng)
+    a = crandn(rng, phi.shape[1], *sens.shape[1:])
+    for c in range(sens.shape[0]):
+        lhs = O.fft2c(sens[c][None] * np.einsum("tk,kyz->tyz", phi, a))
+        rhs = np.einsum("tk,kyz->tyz", phi, O.fft2c(sens[c][None] * a))
+        assert rel(lhs, rhs) < 1e-12
+
+
+# --- T5: space-time kernel route of the normal operator -------------------------------------
+
+
+def test_psi_normal_equals_explicit():
+    rng = np.random.default_rng(8)
+    phi, sens, masks = small_problem(rng)
+    a = crandn(rng, phi.shape[1], *sens.shape[1:])
+    psi = O.space_time_kernel(phi, masks)
+    assert rel(O.normal_psi(a, sens, psi), O.normal_explicit(a, sens, phi, masks)) < 1e-12
+
+
+def test_psi_real_symmetric_and_full_sampling():
+    rng = np.random.default_rng(9)
+    phi, sens, masks = small_problem(rng)
+    psi = O.space_time_kernel(phi, masks)
+    assert np.isrealobj(psi)
+    assert np.array_equal(psi, psi.transpose(1, 0, 2, 3))
+    # brute force one location
+    n = (3, 5)
+    brute = sum(np.outer(phi[t], phi[t]) for t in range(phi.shape[0]) if masks[t][n])
+    assert np.allclose(psi[:, :, n[0], n[1]], brute, atol=1e-14)
+    full = np.ones_like(masks)
+    psi_full = O.space_time_kernel(phi, full)
+    eye = np.eye(phi.shape[1])[:, :, None, None]
+    assert np.allclose(psi_full, eye, atol=1e-13)         # Phi has orthonormal columns
+    a = crandn(rng, phi.shape[1], *sens.shape[1:])
+    assert rel(O.normal_psi(a, sens, psi_full), a) < 1e-12   # SoS coils: A^H A = I
+
+
+# --- T7: LLR prox ------------------------------------------------------------------------------
+
+
+def test_svt_closed_forms():
+    rng = np.random.default_rng(10)
+    B, K = 64, 4
+    u = crandn(rng, B)
+    u /= np.linalg.norm(u)
+    v = crandn(rng, K)
+    v /= np.linalg.norm(v)
+    for sigma, tau in [(3.0, 0.01), (0.5, 0.1), (0.05, 0.1)]:
+        X = sigma * np.outer(u, v.conj())
+        assert rel(O.svt(X, tau) + 1e-300, max(sigma - tau, 0.0) * np.outer(u, v.conj()) + 1e-300) < 1e-12 \
+            or (sigma <= tau and np.abs(O.svt(X, tau)).max() < 1e-14)
+    # prescribed singular values through random unitary factors
+    U, _ = np.linalg.qr(crandn(rng, B, K))
+    V, _ = np.linalg.qr(crandn(rng, K, K))
+    s = np.array([2.0, 0.7, 0.15, 0.02])
+    X = (U * s) @ V.conj().T
+    assert rel(O.svt(X, 0.1), (U * np.maximum(s - 0.1, 0)) @ V.conj().T) < 1e-12
+    assert rel(O.svt(X, 0.0), X) < 1e-12
+    assert np.abs(O.svt(np.zeros((B, K)), 0.1)).max() == 0.0
+    # homogeneity and row permutation equivariance
+    assert rel(O.svt(3.0 * X, 0.3), 3.0 * O.svt(X, 0.1)) < 1e-12
+    perm = rng.permutation(B)
+    assert rel(O.svt(X[perm], 0.1), O.svt(X, 0.1)[perm]) < 1e-12
+
+
+def test_svt_is_the_proximal_map():
+    # SVT minimises 1/2||X - Y||^2 + tau ||X||_*; random perturbations never do better
+    rng = np.random.default_rng(11)
+    Y = crandn(rng, 16, 3)
+    tau = 0.8
+
+    def f(X):
+        return 0.5 * np.linalg.norm(X - Y) ** 2 + tau * np.linalg.svd(X, compute_uv=False).sum()
+
+    X = O.svt(Y, tau)
+    f0 = f(X)
+    for scale in (1e-1, 1e-3):
+        for _ in range(50):
+            assert f(X + scale * crandn(rng, 16, 3)) >= f0 - 1e-12
+
+
+def test_llr_identity_zero_and_single_vs_explicit():
+    rng = np.random.default_rng(12)
+    K, ny, nz, b = 3, 16, 24, 8
+    v = crandn(rng, K, ny, nz)
+    assert rel(O.llr_prox(v, 0.0, (3, 5), b), v) < 1e-12
+    assert np.abs(O.llr_prox(np.zeros_like(v), 0.1, (3, 5), b)).max() == 0.0
+    for shift in [(0, 0), (3, 5), (7, 1)]:
+        assert rel(O.llr_prox(v, 0.7, shift, b), O.llr_prox_explicit(v, 0.7, shift, b)) < 1e-12
+
+
+def test_llr_block_membership_under_shift():
+    # a rank-1 pattern confined to one shifted block is shrunk by exactly tau there and
+    # nothing else moves: pins the block membership rule (rows p*b + i + s_y mod Ny)
+    rng = np.random.default_rng(13)
+    K, ny, nz, b = 2, 16, 16, 4
+    sy, sz = 3, 2
+    v = np.zeros((K, ny, nz), dtype=complex)
+    rows = (1 * b + np.arange(b) + sy) % ny
+    cols = (3 * b + np.arange(b) + sz) % nz        # wraps around
+    uvec = crandn(rng, b * b)
+    uvec /= np.linalg.norm(uvec)
+    wvec = crandn(rng, K)
+    wvec /= np.linalg.norm(wvec)
+    blk = 2.0 * np.outer(uvec, wvec.conj())        # [B, K], sigma = 2
+    v[:, rows[:, None], cols[None, :]] = blk.T.reshape(K, b, b)
+    out = O.llr_prox(v, 0.5, (sy, sz), b)
+    assert rel(out, 0.75 * v) < 1e-12
+    # with a different shift the pattern straddles blocks: no longer a pure rescale
+    out2 = O.llr_prox(v, 0.5, (0, 0), b)
+    assert rel(out2, 0.75 * v) > 1e-3
+
+
+def test_llr_value_matches_svd():
+    rng = np.random.default_rng(14)
+    v = crandn(rng, 2, 8, 8)
+    val = O.llr_value(v, (1, 2), 4)
+    brute = 0.0
+    w = np.roll(v, (-1, -2), axis=(1, 2))
+    for p in range(2):
+        for q in range(2):
+            X = w[:, 4 * p:4 * p + 4, 4 * q:4 * q + 4].reshape(2, 16).T
+            brute += np.linalg.svd(X, compute_uv=False).sum()
+    assert abs(val - brute) < 1e-12 * brute
+
+
+# --- T9: CG ---------------------------------------------------------------------------------
+
+
+def test_cg_solves_hpd_system():
+    rng = np.random.default_rng(15)
+    n = 12
+    Q = crandn(rng, n, n)
+    M = Q @ Q.conj().T + 0.5 * np.eye(n)
+    b = crandn(rng, n)
+    x = O.cg(lambda v: M @ v, np.zeros(n, dtype=complex), b, 3 * n)
+    assert rel(x, np.linalg.solve(M, b)) < 1e-10
+    # a few iterations reduce the M-norm error monotonically
+    xs = [O.cg(lambda v: M @ v, np.zeros(n, dtype=complex), b, k) for k in range(1, 6)]
+    xt = np.linalg.solve(M, b)
+    errs = [np.vdot(x - xt, M @ (x - xt)).real for x in xs]
+    assert all(e1 <= e0 * (1 + 1e-12) for e0, e1 in zip(errs, errs[1:]))
+
+
+def test_cg_one_step_exact_for_scaled_identity():
+    rng = np.random.default_rng(16)
+    phi, sens, _ = small_problem(rng)
+    full = np.ones((phi.shape[0],) + sens.shape[1:], dtype=bool)
+    psi = O.space_time_kernel(phi, full)
+    rho = 0.1
+    b = crandn(rng, phi.shape[1], *sens.shape[1:])
+    x = O.cg(lambda v: O.normal_psi(v, sens, psi) + rho * v, np.zeros_like(b), b, 1)
+    assert rel(x, b / (1 + rho)) < 1e-12
+
+
+# --- T12: shift schedule -------------------------------------------------------------------
+
+
+def test_splitmix64_golden():
+    vals = [int(l) for l in open(os.path.join(HERE, "golden", "splitmix64_seed1234567.txt"))
+            if l.strip() and not l.startswith("#")]
+    state, M = 1234567, (1 << 64) - 1
+    for v in vals:
+        assert O.splitmix64(state) == v
+        state = (state + 0x9E3779B97F4A7C15) & M
+
+
+def test_block_shift_range_and_spread():
+    seen = set()
+    for k in range(400):
+        sy, sz = O.block_shift(0, 3, k, 8)
+        assert 0 <= sy < 8 and 0 <= sz < 8
+        seen.add((sy, sz))
+    assert len(seen) > 50
+    assert O.block_shift(1, 0, 0, 8) != O.block_shift(1, 1, 0, 8) or O.block_shift(1, 0, 1, 8) != O.block_shift(1, 1, 1, 8)
+
+
+# --- T10 / T11: ADMM ------------------------------------------------------------------------
+
+
+def test_admm_exact_recovery_full_sampling():
+    rng = np.random.default_rng(17)
+    phi, sens, _ = small_problem(rng, ny=16, nz=16)
+    full = np.ones((phi.shape[0], 16, 16), dtype=bool)
+    a_true = crandn(rng, phi.shape[1], 16, 16)
+    y = O.forward(a_true, sens, phi, full)
+    res = O.admm(y, sens, phi, full, lam=0.0, rho=0.1, b=8, n_outer=12, n_cg=5, seed=0)
+    assert rel(res.alpha, a_true) < 1e-10
+
+
+def _explicit_matrix(sens, phi, masks):
+    K = phi.shape[1]
+    ny, nz = sens.shape[1:]
+    cols = []
+    for i in range(K * ny * nz):
+        e = np.zeros(K * ny * nz, dtype=complex)
+        e[i] = 1.0
+        cols.append(O.forward(e.reshape(K, ny, nz), sens, phi, masks).reshape(-1))
+    return np.stack(cols, axis=1)
+
+
+def test_admm_lambda0_is_min_norm_least_squares():
+    rng = np.random.default_rng(18)
+    phi, sens, masks = small_problem(rng, ny=8, nz=8, C=2, T=4, K=2, frac=0.5)
+    A = _explicit_matrix(sens, phi, masks)
+    y = crandn(rng, 2, int(masks.sum()))
+    x_ls = np.linalg.lstsq(A, y.reshape(-1), rcond=None)[0]
+    res = O.admm(y, sens, phi, masks, lam=0.0, rho=0.1, b=4, n_outer=400, n_cg=20, seed=0)
+    assert rel(res.alpha.reshape(-1), x_ls) < 1e-8
+
+
+@pytest.mark.slow
+def test_admm_matches_fista_objective_at_fixed_shift():
+    rng = np.random.default_rng(19)
+    phi, sens, masks = small_problem(rng, ny=8, nz=8, C=2, T=4, K=2, frac=0.35)
+    a_true = crandn(rng, 2, 8, 8)
+    y = O.forward(a_true, sens, phi, masks) + 0.05 * crandn(rng, 2, int(masks.sum()))
+    lam, shift = 0.3, (1, 3)
+    r_admm = O.admm(y, sens, phi, masks, lam=lam, rho=0.5, b=4, n_outer=3000, n_cg=20, seed=0,
+                    fixed_shift=shift)
+    x_f = O.fista(y, sens, phi, masks, lam=lam, b=4, n_iter=6000, shift=shift)
+    fa = O.objective(r_admm.alpha, y, sens, phi, masks, lam, shift, 4)
+    ff = O.objective(x_f, y, sens, phi, masks, lam, shift, 4)
+    assert abs(fa - ff) / abs(ff) < 1e-8
+
+
+def test_admm_tolerance_mode_rules():
+    # freeze happens only at check points and the run stops once frozen and converged
+    rng = np.random.default_rng(20)
+    phi, sens, masks = small_problem(rng, ny=16, nz=16, C=2, T=4, K=2, frac=0.4)
+    a_true = crandn(rng, 2, 16, 16)
+    y = O.forward(a_true, sens, phi, masks)
+    res = O.admm(y, sens, phi, masks, lam=0.01, rho=0.1, b=8, n_outer=300, n_cg=5, seed=4,
+                 tol=1e-4, check_every=5)
+    assert res.k_freeze >= 0 and (res.k_freeze + 1) % 5 == 0
+    assert res.n_outer % 5 == 0 and res.n_outer < 300
+    assert res.history[-1]["res"] <= 1e-4
+    shifts_after = {h["shift"] for h in res.history[res.k_freeze:]}
+    assert len(shifts_after) == 1
