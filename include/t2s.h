@@ -1,0 +1,192 @@
+/*
+ * t2s.h -- C ABI of the MI355X (gfx950) T2-Shuffling slice reconstruction library.
+ *
+ * The library solves, independently for every readout slice, the subspace-
+ * constrained PICS problem of the paper (Anderson, Tamir et al., arXiv 1809.04195,
+ * Sec. II-B, eq. t2shpics):
+ *
+ *     argmin_alpha  1/2 || y - P F S Phi alpha ||_2^2  +  lambda * sum_blocks || R(alpha) ||_*
+ *
+ * with y the measured k-space samples of every echo and coil in truncated form
+ * (Sec. II-A: P in {0,1}^{P x N}), S the coil maps, F the centred unitary 2D DFT,
+ * Phi in R^{T x K} the temporal basis (eq. backproj) and R the extraction of
+ * non-overlapping b x b blocks of the K coefficient images under a random circular
+ * shift drawn anew every iteration (Sec. II-B, end; single-pass form Sec. IV-C).
+ * The solver is scaled ADMM whose alpha-step runs CG on A^H A + rho I, with the
+ * normal operator applied through the space-time kernel Psi(n) = Phi^T P(n) Phi
+ * (Sec. IV-B, eqs. commute / normaleq, Alg. 1).
+ *
+ * Conventions
+ * -----------
+ *  * Return value: 0 = success, > 0 = warning, < 0 = error (T2S_E*).  The message
+ *    of the last non-zero return of the calling thread is t2s_last_error().
+ *  * Complex data are complex64: interleaved (re, im) float32 pairs.
+ *  * Image-domain arrays are row-major [..][ny][nz] (nz contiguous).  Mask and
+ *    k-space index j means frequency j - n/2 (centred; DC at (ny/2, nz/2)).
+ *  * Samples ("ksp") of one slice are [ncoils][P_tot] in mask order: echo-major,
+ *    then row-major (y, z) position inside the echo's mask.
+ *  * `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    Calls are stream-ordered and asynchronous unless stated otherwise.
+ *  * `mem` is T2S_HOST or T2S_DEVICE and says where a caller buffer lives.
+ *    Host buffers are copied before the call returns.  Device buffers must stay
+ *    valid until the stream has executed the operation.  The library never frees
+ *    caller memory.
+ *  * Argument validation (shapes, pointers, finiteness of host inputs) happens
+ *    before any HIP call, so every error path can be exercised without a GPU.
+ *  * A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef T2S_H
+#define T2S_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define T2S_OK 0
+#define T2S_WNOTCONVERGED 1   /* tolerance mode: some slice hit n_outer before tol   */
+#define T2S_EINVAL (-1)       /* null pointer, bad enum, bad numeric parameter       */
+#define T2S_ESHAPE (-2)       /* odd or non-multiple-of-block dims, K > 8, K > T ... */
+#define T2S_ENOMEM (-3)       /* workspace missing or too small                      */
+#define T2S_EHIP (-4)         /* HIP runtime error (message carries its text)        */
+#define T2S_ESTATE (-5)       /* call out of order (e.g. reconstruct before load)    */
+#define T2S_ENONFINITE (-6)   /* NaN / Inf in Phi, parameters, maps or samples       */
+#define T2S_EUNSUPPORTED (-7) /* grid length without a compiled FFT plan             */
+
+#define T2S_HOST 0
+#define T2S_DEVICE 1
+
+#define T2S_BATCHED 0   /* every launch covers all loaded slices of a shape class */
+#define T2S_PER_SLICE 1 /* one launch sequence per slice (baseline schedule)      */
+
+#define T2S_ALPHA 0
+#define T2S_Z 1
+#define T2S_U 2
+#define T2S_ADJOINT 3   /* b0 = A^H y of the loaded samples */
+
+#define T2S_MAX_K 8
+
+/* Solver parameters shared by all shape classes of a plan. */
+typedef struct t2s_params {
+    int T;                 /* echoes (rows of phi)                                   */
+    int K;                 /* subspace size (columns of phi), 1..T2S_MAX_K, K <= T   */
+    const float* phi;      /* host, real [T][K] row-major; copied at plan creation   */
+    float lambda;          /* LLR weight (absolute; data are not rescaled)           */
+    float rho;             /* ADMM penalty; LLR threshold is lambda / rho            */
+    int block;             /* LLR block edge b (ny, nz multiples of b)               */
+    int n_outer;           /* outer iterations (fixed mode) or cap (tolerance mode)  */
+    int n_cg;              /* CG iterations per outer iteration (>= 1)               */
+    float tol;             /* 0: fixed iterations; > 0: stop at max(r_p, r_d) <= tol */
+    uint64_t seed;         /* block-shift schedule seed (SplitMix64)                 */
+    int freeze_window;     /* tolerance mode: stall window (outer iterations)        */
+    float freeze_stall;    /* tolerance mode: relative fall below which shifts freeze */
+    int check_every;       /* tolerance mode: decisions every this many iterations   */
+} t2s_params;
+
+/* One shape class: slices sharing grid, coil count and sampling masks. */
+typedef struct t2s_class {
+    int ny, nz;            /* slice grid (even, multiples of block)                  */
+    int ncoils;            /* C >= 1                                                 */
+    int nslices;           /* slices of this class held by the plan                  */
+    const uint8_t* masks;  /* host [T][ny][nz], 1 = sampled; copied at creation      */
+} t2s_class;
+
+/* Per-slice outcome of the last t2s_reconstruct. */
+typedef struct t2s_slice_report {
+    int outer_iterations;  /* outer iterations run                                   */
+    int k_freeze;          /* outer index whose shift was frozen (-1: never)         */
+    int converged;         /* tolerance mode: 1 if max(r_p, r_d) <= tol             */
+    double r_primal;       /* ||alpha - z|| / max(||alpha||, ||z||) after the last outer */
+    double r_dual;         /* rho ||z - z_prev|| / ||rho u|| (inf while u = 0)       */
+} t2s_slice_report;
+
+typedef struct t2s_plan t2s_plan;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int t2s_version(void);
+
+/* Thread-local message for the last non-zero return (never NULL). */
+const char* t2s_last_error(void);
+
+/* Validate parameters and classes, build the host-side plan: the space-time kernel
+ * Psi(n) = sum_{t: m_t(n)=1} phi_t^T phi_t (Sec. IV-B) in FP64, stored as its upper
+ * triangle (k <= l), real, shifted to uncentred FFT order and scaled by 1/(ny nz)
+ * (fp32), and the location -> sample map used to project the samples onto the
+ * basis (Sec. III-A, "re-sort and project").  No HIP call is made.
+ * Errors: T2S_EINVAL, T2S_ESHAPE, T2S_ENONFINITE, T2S_EUNSUPPORTED. */
+int t2s_plan_create(const t2s_params* params, const t2s_class* classes, int n_classes,
+                    t2s_plan** out);
+
+/* Free host state.  Device memory is the caller's and is not touched. */
+int t2s_plan_destroy(t2s_plan* plan);
+
+/* Device workspace (bytes) needed by the plan: kernel tables, per-slice coil maps,
+ * samples, solver vectors and pass intermediates. */
+int t2s_plan_workspace_bytes(const t2s_plan* plan, size_t* bytes);
+
+/* Bind caller-owned device memory (>= t2s_plan_workspace_bytes, 256-byte aligned)
+ * and upload the plan tables on `stream`.  Errors: T2S_ENOMEM, T2S_EHIP. */
+int t2s_plan_bind_workspace(t2s_plan* plan, void* device_ptr, size_t bytes, void* stream);
+
+/* Load slices [first, first + count) of class `cls`: coil maps sens
+ * (complex64 [count][ncoils][ny][nz]) and samples ksp (complex64
+ * [count][ncoils][P_tot], mask order), both in `mem`, and compute the adjoint
+ * b0 = A^H y = sum_c conj(S_c) F^H (Phi^T P^H y_c) on the device.  Resets the
+ * slices to the cold start alpha = z = u = 0.  Host inputs are checked for
+ * NaN / Inf (T2S_ENONFINITE). */
+int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* sens,
+                    const void* ksp, int mem, void* stream);
+
+/* Warm start: alpha = z = alpha0 (complex64 [count][K][ny][nz] in `mem`), u = 0.
+ * Must follow t2s_load_slices for these slices. */
+int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* alpha0,
+                    int mem, void* stream);
+
+/* Run ADMM on every loaded slice.  mode = T2S_BATCHED or T2S_PER_SLICE (same
+ * arithmetic, different launch schedule).  Fixed mode (tol == 0) is fully
+ * asynchronous.  Tolerance mode synchronises `stream` every check_every outer
+ * iterations to read the per-slice residuals, and returns T2S_WNOTCONVERGED if a
+ * slice reached n_outer without meeting tol. */
+int t2s_reconstruct(t2s_plan* plan, int mode, void* stream);
+
+/* Copy out alpha, z, u or b0 (which = T2S_ALPHA / T2S_Z / T2S_U / T2S_ADJOINT) of
+ * slices [first, first + count) as complex64 [count][K][ny][nz] into `out` (`mem`).
+ * A host destination synchronises `stream`. */
+int t2s_read_coeffs(t2s_plan* plan, int cls, int first, int count, void* out, int which,
+                    int mem, void* stream);
+
+/* Per-slice report of the last reconstruct (synchronous host call; call after the
+ * stream has finished the reconstruct). */
+int t2s_get_slice_report(const t2s_plan* plan, int cls, int slice, t2s_slice_report* out);
+
+/* ---- Operator entry points (same kernels as the solver; used for verification) ---- */
+
+/* out = A^H A in + rho_add * in for slices [first, first + count) of `cls`, using
+ * their loaded coil maps and the class's Psi (Sec. IV-B, Alg. 1).  `in`, `out`:
+ * device complex64 [count][K][ny][nz], must not overlap. */
+int t2s_apply_normal(t2s_plan* plan, int cls, int first, int count, const void* in,
+                     void* out, float rho_add, void* stream);
+
+/* out = LLR prox with threshold tau of `in` (device complex64 [count][K][ny][nz]):
+ * every non-overlapping b x b block of the K images, shifted by shifts[2 i],
+ * shifts[2 i + 1] (host int, s_y, s_z in [0, b)) for slice i, replaced by its
+ * singular-value soft threshold (Sec. II-B eq. llr; single pass of Sec. IV-C). */
+int t2s_apply_llr(t2s_plan* plan, int cls, int first, int count, const void* in, void* out,
+                  float tau, const int* shifts, void* stream);
+
+/* Copy the class's fp32 kernel table (upper triangle, [K(K+1)/2][nz][ny] in
+ * uncentred order, scaled by 1/(ny nz)) into host memory `out`. */
+int t2s_get_psi(const t2s_plan* plan, int cls, float* out);
+
+/* The library's own block-shift schedule: SplitMix64 (Steele, Lea & Flood 2014),
+ * h = sm(sm(sm(seed) ^ g) ^ k), s_y = (h mod 2^32) mod b, s_z = (h >> 32) mod b, for
+ * global slice index g (class-major order) and outer iteration k.  Host only. */
+int t2s_block_shift(uint64_t seed, int g, int k, int b, int* sy, int* sz);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* T2S_H */

@@ -1,0 +1,323 @@
+"""Python binding of ``libt2s.so`` (the gfx950 T2-Shuffling slice solver).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels behind the C ABI declared in ``include/t2s.h``.  The functions below have
+the same names as the C entry points.  PyTorch is used for device memory (the
+workspace, device-resident inputs and outputs) and for streams.
+
+If the shared library has not been built, importing works but every call raises
+``RuntimeError`` -- there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libt2s.so")
+
+T2S_OK = 0
+T2S_WNOTCONVERGED = 1
+T2S_EINVAL = -1
+T2S_ESHAPE = -2
+T2S_ENOMEM = -3
+T2S_EHIP = -4
+T2S_ESTATE = -5
+T2S_ENONFINITE = -6
+T2S_EUNSUPPORTED = -7
+T2S_HOST = 0
+T2S_DEVICE = 1
+T2S_BATCHED = 0
+T2S_PER_SLICE = 1
+T2S_ALPHA = 0
+T2S_Z = 1
+T2S_U = 2
+T2S_ADJOINT = 3
+
+
+class t2s_params(ctypes.Structure):
+    _fields_ = [
+        ("T", ctypes.c_int),
+        ("K", ctypes.c_int),
+        ("phi", ctypes.POINTER(ctypes.c_float)),
+        ("lambda_", ctypes.c_float),
+        ("rho", ctypes.c_float),
+        ("block", ctypes.c_int),
+        ("n_outer", ctypes.c_int),
+        ("n_cg", ctypes.c_int),
+        ("tol", ctypes.c_float),
+        ("seed", ctypes.c_uint64),
+        ("freeze_window", ctypes.c_int),
+        ("freeze_stall", ctypes.c_float),
+        ("check_every", ctypes.c_int),
+    ]
+
+
+class t2s_class(ctypes.Structure):
+    _fields_ = [
+        ("ny", ctypes.c_int),
+        ("nz", ctypes.c_int),
+        ("ncoils", ctypes.c_int),
+        ("nslices", ctypes.c_int),
+        ("masks", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
+class t2s_slice_report(ctypes.Structure):
+    _fields_ = [
+        ("outer_iterations", ctypes.c_int),
+        ("k_freeze", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("r_primal", ctypes.c_double),
+        ("r_dual", ctypes.c_double),
+    ]
+
+
+class T2SError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"t2s error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_SIGS = {
+    "t2s_version": ([], ctypes.c_int),
+    "t2s_last_error": ([], ctypes.c_char_p),
+    "t2s_plan_create": ([ctypes.POINTER(t2s_params), ctypes.POINTER(t2s_class), ctypes.c_int,
+                         ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "t2s_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "t2s_plan_workspace_bytes": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "t2s_plan_bind_workspace": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "t2s_load_slices": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "t2s_set_initial": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                         ctypes.c_void_p], ctypes.c_int),
+    "t2s_reconstruct": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "t2s_read_coeffs": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                         ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "t2s_get_slice_report": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(t2s_slice_report)],
+                             ctypes.c_int),
+    "t2s_apply_normal": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p], ctypes.c_int),
+    "t2s_apply_llr": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_float, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p], ctypes.c_int),
+    "t2s_get_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "t2s_block_shift": ([ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                         ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libt2s.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no non-HIP implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code, allow_warn=False):
+    if code < 0 or (code > 0 and not allow_warn):
+        raise T2SError(code, lib().t2s_last_error().decode())
+    return code
+
+
+def _ptr(x):
+    """Raw address of a numpy array (host) or torch tensor (device or host)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def _mem(x):
+    if hasattr(x, "is_cuda") and x.is_cuda:
+        return T2S_DEVICE
+    return T2S_HOST
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+# ---- thin wrappers with the C names ----------------------------------------------
+
+
+def t2s_version():
+    return lib().t2s_version()
+
+
+def t2s_last_error():
+    return lib().t2s_last_error().decode()
+
+
+def t2s_block_shift(seed, g, k, b):
+    sy, sz = ctypes.c_int(), ctypes.c_int()
+    _check(lib().t2s_block_shift(ctypes.c_uint64(seed), g, k, b, ctypes.byref(sy), ctypes.byref(sz)))
+    return sy.value, sz.value
+
+
+def make_params(phi, lam, rho, block=8, n_outer=20, n_cg=5, tol=0.0, seed=0, freeze_window=5,
+                freeze_stall=0.05, check_every=5):
+    phi = np.ascontiguousarray(phi, dtype=np.float32)
+    p = t2s_params(T=phi.shape[0], K=phi.shape[1], phi=phi.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                   lambda_=lam, rho=rho, block=block, n_outer=n_outer, n_cg=n_cg, tol=tol, seed=seed,
+                   freeze_window=freeze_window, freeze_stall=freeze_stall, check_every=check_every)
+    p._keep = phi
+    return p
+
+
+def make_classes(classes):
+    """classes: list of (ny, nz, ncoils, nslices, masks uint8 [T, ny, nz])."""
+    arr = (t2s_class * len(classes))()
+    keep = []
+    for i, (ny, nz, nc, ns, masks) in enumerate(classes):
+        m = np.ascontiguousarray(masks, dtype=np.uint8)
+        keep.append(m)
+        arr[i] = t2s_class(ny=ny, nz=nz, ncoils=nc, nslices=ns,
+                           masks=m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return arr, keep
+
+
+def t2s_plan_create(params, classes_arr, n_classes):
+    h = ctypes.c_void_p()
+    _check(lib().t2s_plan_create(ctypes.byref(params), classes_arr, n_classes, ctypes.byref(h)))
+    return h
+
+
+def t2s_plan_destroy(plan):
+    return _check(lib().t2s_plan_destroy(plan))
+
+
+def t2s_plan_workspace_bytes(plan):
+    n = ctypes.c_size_t()
+    _check(lib().t2s_plan_workspace_bytes(plan, ctypes.byref(n)))
+    return n.value
+
+
+def t2s_plan_bind_workspace(plan, ptr, nbytes, stream=None):
+    return _check(lib().t2s_plan_bind_workspace(plan, ptr, nbytes, _stream(stream)))
+
+
+def t2s_load_slices(plan, cls, first, count, sens, ksp, stream=None):
+    return _check(lib().t2s_load_slices(plan, cls, first, count, _ptr(sens), _ptr(ksp), _mem(sens), _stream(stream)))
+
+
+def t2s_set_initial(plan, cls, first, count, alpha0, stream=None):
+    return _check(lib().t2s_set_initial(plan, cls, first, count, _ptr(alpha0), _mem(alpha0), _stream(stream)))
+
+
+def t2s_reconstruct(plan, mode=T2S_BATCHED, stream=None):
+    return _check(lib().t2s_reconstruct(plan, mode, _stream(stream)), allow_warn=True)
+
+
+def t2s_read_coeffs(plan, cls, first, count, out, which=T2S_ALPHA, stream=None):
+    return _check(lib().t2s_read_coeffs(plan, cls, first, count, _ptr(out), which, _mem(out), _stream(stream)))
+
+
+def t2s_get_slice_report(plan, cls, slice_):
+    r = t2s_slice_report()
+    _check(lib().t2s_get_slice_report(plan, cls, slice_, ctypes.byref(r)))
+    return dict(outer_iterations=r.outer_iterations, k_freeze=r.k_freeze, converged=r.converged,
+                r_primal=r.r_primal, r_dual=r.r_dual)
+
+
+def t2s_apply_normal(plan, cls, first, count, inp, out, rho_add=0.0, stream=None):
+    return _check(lib().t2s_apply_normal(plan, cls, first, count, _ptr(inp), _ptr(out), rho_add, _stream(stream)))
+
+
+def t2s_apply_llr(plan, cls, first, count, inp, out, tau, shifts, stream=None):
+    sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.int32).reshape(-1))
+    return _check(lib().t2s_apply_llr(plan, cls, first, count, _ptr(inp), _ptr(out), tau,
+                                      sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _stream(stream)))
+
+
+def t2s_get_psi(plan, cls, K, ny, nz):
+    out = np.empty((K * (K + 1) // 2, nz, ny), dtype=np.float32)
+    _check(lib().t2s_get_psi(plan, cls, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+# ---- convenience object -------------------------------------------------------------
+
+
+class Plan:
+    """A plan plus its torch-allocated workspace.
+
+    classes: list of dicts with keys ny, nz, ncoils, nslices, masks.
+    """
+
+    def __init__(self, phi, classes, lam, rho, block=8, n_outer=20, n_cg=5, tol=0.0, seed=0,
+                 freeze_window=5, freeze_stall=0.05, check_every=5, device="cuda"):
+        import torch
+        self.phi = np.ascontiguousarray(phi, dtype=np.float32)
+        self.K = self.phi.shape[1]
+        self.classes = classes
+        self._params = make_params(self.phi, lam, rho, block, n_outer, n_cg, tol, seed, freeze_window,
+                                   freeze_stall, check_every)
+        arr, self._keep = make_classes([(c["ny"], c["nz"], c["ncoils"], c["nslices"], c["masks"]) for c in classes])
+        self.handle = t2s_plan_create(self._params, arr, len(classes))
+        self.nbytes = t2s_plan_workspace_bytes(self.handle)
+        self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        t2s_plan_bind_workspace(self.handle, aligned, self.nbytes)
+
+    def load(self, cls, first, sens, ksp, stream=None):
+        return t2s_load_slices(self.handle, cls, first, sens.shape[0], sens, ksp, stream)
+
+    def set_initial(self, cls, first, alpha0, stream=None):
+        return t2s_set_initial(self.handle, cls, first, alpha0.shape[0], alpha0, stream)
+
+    def reconstruct(self, mode=T2S_BATCHED, stream=None):
+        return t2s_reconstruct(self.handle, mode, stream)
+
+    def read(self, cls, first, count, which=T2S_ALPHA, device=False, stream=None):
+        c = self.classes[cls]
+        shape = (count, self.K, c["ny"], c["nz"])
+        if device:
+            import torch
+            out = torch.empty(shape, dtype=torch.complex64, device="cuda")
+        else:
+            out = np.empty(shape, dtype=np.complex64)
+        t2s_read_coeffs(self.handle, cls, first, count, out, which, stream)
+        return out
+
+    def report(self, cls, s):
+        return t2s_get_slice_report(self.handle, cls, s)
+
+    def close(self):
+        if self.handle is not None:
+            t2s_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

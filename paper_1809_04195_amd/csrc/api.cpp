@@ -1,0 +1,610 @@
+// api.cpp -- C ABI of the T2-Shuffling slice solver: validation, plan tables,
+// workspace layout and the ADMM / CG launch schedule.  See include/t2s.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/t2s.h"
+#include "kernels.hpp"
+
+using t2s::ClassArgs;
+using t2s::PartialSrc;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(T2S_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct ClassPlan {
+    int ny = 0, nz = 0, C = 0, S = 0, P = 0, gbase = 0;
+    int npw = 0, nrr = 0, nllr = 0;
+    std::vector<float> psi;                 // [K(K+1)/2][nz][ny]
+    std::vector<int> row_ptr, ent_t, ent_p;
+    std::vector<float> twy, twz;            // interleaved (re, im)
+    size_t o_psi = 0, o_twy = 0, o_twz = 0, o_phi = 0, o_rowptr = 0, o_entt = 0, o_entp = 0;
+    size_t o_sens = 0, o_ksp = 0, o_vec[7] = {}, o_tmp = 0, o_pw = 0, o_rr = 0, o_g0 = 0, o_llr = 0,
+           o_hist = 0, o_state = 0;
+    std::vector<int> loaded;
+    std::vector<int> outer_run, k_freeze, converged;
+    ClassArgs args{};
+};
+
+}  // namespace
+
+struct t2s_plan {
+    t2s_params prm{};
+    std::vector<float> phi;
+    std::vector<ClassPlan> cls;
+    size_t ws_bytes = 0;
+    char* ws = nullptr;
+    bool bound = false;
+    int hist_len = 0;
+    bool reconstructed = false;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+int check_class_index(const t2s_plan* plan, int cls, int first, int count) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
+    const ClassPlan& c = plan->cls[cls];
+    if (count < 1 || first < 0 || first + count > c.S) return fail(T2S_EINVAL, "slice range out of bounds");
+    return 0;
+}
+
+void roots(int L, std::vector<float>& out) {
+    out.resize(2 * L);
+    for (int m = 0; m < L; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)L;
+        out[2 * m] = (float)std::cos(a);
+        out[2 * m + 1] = (float)std::sin(a);
+    }
+}
+
+size_t vec_bytes(const ClassPlan& c, int K) { return (size_t)c.S * K * c.ny * c.nz * 8; }
+
+void fill_args(t2s_plan* plan, ClassPlan& c) {
+    char* b = plan->ws;
+    ClassArgs& a = c.args;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    a.C = c.C;
+    a.K = plan->prm.K;
+    a.T = plan->prm.T;
+    a.P = c.P;
+    a.npw = c.npw;
+    a.nrr = c.nrr;
+    a.nllr = c.nllr;
+    a.gbase = c.gbase;
+    a.hist_len = plan->hist_len;
+    a.block = plan->prm.block;
+    a.tau = plan->prm.lambda / plan->prm.rho;
+    a.rho = plan->prm.rho;
+    a.seed = plan->prm.seed;
+    a.psi = (const float*)(b + c.o_psi);
+    a.twy = (const float2*)(b + c.o_twy);
+    a.twz = (const float2*)(b + c.o_twz);
+    a.phi = (const float*)(b + c.o_phi);
+    a.row_ptr = (const int*)(b + c.o_rowptr);
+    a.ent_t = (const int*)(b + c.o_entt);
+    a.ent_p = (const int*)(b + c.o_entp);
+    a.sens = (float2*)(b + c.o_sens);
+    a.ksp = (float2*)(b + c.o_ksp);
+    a.b0 = (float2*)(b + c.o_vec[0]);
+    a.x = (float2*)(b + c.o_vec[1]);
+    a.r = (float2*)(b + c.o_vec[2]);
+    a.p = (float2*)(b + c.o_vec[3]);
+    a.w = (float2*)(b + c.o_vec[4]);
+    a.z = (float2*)(b + c.o_vec[5]);
+    a.u = (float2*)(b + c.o_vec[6]);
+    a.tmp = (float2*)(b + c.o_tmp);
+    a.pw = (double*)(b + c.o_pw);
+    a.rr = (double*)(b + c.o_rr);
+    a.g0 = (double*)(b + c.o_g0);
+    a.llr = (double*)(b + c.o_llr);
+    a.hist = (double*)(b + c.o_hist);
+    a.state = (int*)(b + c.o_state);
+}
+
+PartialSrc rr_src(const ClassArgs& a, int buf) { return PartialSrc{a.rr + (size_t)buf * a.nrr, 2 * a.nrr, a.nrr}; }
+PartialSrc g0_src(const ClassArgs& a) { return PartialSrc{a.g0, a.nllr, a.nllr}; }
+
+#define HIP_CHECK_LAUNCH(expr)                                                                 \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(T2S_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_));     \
+    } while (0)
+
+// w = (A^H A + rho_add) applied to src (slices [s0, s0+count), src indexed from src_s0)
+int run_normal(const ClassArgs& a, int s0, int count, const float2* src, int src_s0, float rho_add, float2* out,
+               int out_s0, hipStream_t st) {
+    HIP_CHECK_LAUNCH(t2s::launch_passA(a, s0, count, src, src_s0, 1, PartialSrc{nullptr, 0, 0},
+                                       PartialSrc{nullptr, 0, 0}, st));
+    HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, st));
+    HIP_CHECK_LAUNCH(t2s::launch_passC(a, s0, count, 0, rho_add, out, out_s0, st));
+    return 0;
+}
+
+// one ADMM outer iteration k for slices [s0, s0 + count)
+int run_outer(const t2s_plan* plan, const ClassArgs& a, int s0, int count, int k, hipStream_t st) {
+    const int ncg = plan->prm.n_cg;
+    for (int i = 0; i < ncg; ++i) {
+        const PartialSrc none{nullptr, 0, 0};
+        const PartialSrc gcA = (i == 0) ? none : rr_src(a, i % 2);
+        const PartialSrc gpA = (i == 0) ? none : (i == 1 ? g0_src(a) : rr_src(a, (i - 1) % 2));
+        HIP_CHECK_LAUNCH(t2s::launch_passA(a, s0, count, a.r, 0, i == 0 ? 1 : 0, gcA, gpA, st));
+        HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_passC(a, s0, count, 0, a.rho, a.w, 0, st));
+        const PartialSrc gcU = (i == 0) ? g0_src(a) : rr_src(a, i % 2);
+        HIP_CHECK_LAUNCH(t2s::launch_cg_update(a, s0, count, gcU, (i + 1) % 2, st));
+    }
+    HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrAdmm, k, nullptr, nullptr, a.tau, 0, 0, st));
+    HIP_CHECK_LAUNCH(t2s::launch_llr_finalize(a, s0, count, k, st));
+    return 0;
+}
+
+void residuals_from_hist(const double* h, double rho, double* rp, double* rd) {
+    const double na = std::sqrt(h[2]), nzz = std::sqrt(h[3]);
+    const double den = std::max(na, nzz);
+    *rp = den > 0 ? std::sqrt(h[0]) / den : 0.0;
+    const double nu = rho * std::sqrt(h[4]);
+    *rd = nu > 0 ? rho * std::sqrt(h[1]) / nu : std::numeric_limits<double>::infinity();
+}
+
+}  // namespace
+
+extern "C" {
+
+int t2s_version(void) { return 100; }
+
+const char* t2s_last_error(void) { return g_err.c_str(); }
+
+int t2s_block_shift(uint64_t seed, int g, int k, int b, int* sy, int* sz) {
+    if (!sy || !sz) return fail(T2S_EINVAL, "null output");
+    if (b < 1 || g < 0 || k < 0) return fail(T2S_EINVAL, "bad block shift arguments");
+    auto sm = [](uint64_t x) {
+        uint64_t z = x + 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    const uint64_t h = sm(sm(sm(seed) ^ (uint64_t)g) ^ (uint64_t)k);
+    *sy = (int)((h & 0xFFFFFFFFull) % (uint64_t)b);
+    *sz = (int)((h >> 32) % (uint64_t)b);
+    return 0;
+}
+
+int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes, t2s_plan** out) {
+    if (!out) return fail(T2S_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(T2S_EINVAL, "params is NULL");
+    if (!p->phi) return fail(T2S_EINVAL, "phi is NULL");
+    if (!classes || n_classes < 1) return fail(T2S_EINVAL, "no shape classes");
+    if (p->T < 1) return fail(T2S_ESHAPE, "T must be >= 1");
+    if (p->K < 1 || p->K > T2S_MAX_K) return fail(T2S_ESHAPE, "K must be in [1, 8]");
+    if (p->K > p->T) return fail(T2S_ESHAPE, "K must not exceed T");
+    if (!finite_f(p->lambda) || !finite_f(p->rho) || !finite_f(p->tol) || !finite_f(p->freeze_stall))
+        return fail(T2S_ENONFINITE, "non-finite solver parameter");
+    if (p->lambda < 0) return fail(T2S_EINVAL, "lambda must be >= 0");
+    if (!(p->rho > 0)) return fail(T2S_EINVAL, "rho must be > 0");
+    if (p->block != 4 && p->block != 8 && p->block != 16) return fail(T2S_EINVAL, "block must be 4, 8 or 16");
+    if (p->n_outer < 1 || p->n_cg < 1) return fail(T2S_EINVAL, "n_outer and n_cg must be >= 1");
+    if (p->tol < 0) return fail(T2S_EINVAL, "tol must be >= 0");
+    if (p->tol > 0 && (p->freeze_window < 1 || p->check_every < 1 || p->freeze_stall < 0 || p->freeze_stall >= 1))
+        return fail(T2S_EINVAL, "tolerance mode needs freeze_window >= 1, check_every >= 1, 0 <= freeze_stall < 1");
+    const int T = p->T, K = p->K;
+    for (int i = 0; i < T * K; ++i)
+        if (!finite_f(p->phi[i])) return fail(T2S_ENONFINITE, "phi has NaN/Inf");
+    for (int ci = 0; ci < n_classes; ++ci) {
+        const t2s_class& c = classes[ci];
+        if (!c.masks) return fail(T2S_EINVAL, "class " + std::to_string(ci) + ": masks is NULL");
+        if (c.ncoils < 1 || c.nslices < 1) return fail(T2S_ESHAPE, "class " + std::to_string(ci) + ": ncoils and nslices must be >= 1");
+        if (c.ny < 16 || c.nz < 16 || c.ny % 16 || c.nz % 16 || c.ny % p->block || c.nz % p->block)
+            return fail(T2S_ESHAPE, "class " + std::to_string(ci) + ": ny, nz must be multiples of 16 and of block");
+        if (!t2s::fft_supported(c.ny) || !t2s::fft_supported(c.nz))
+            return fail(T2S_EUNSUPPORTED, "class " + std::to_string(ci) + ": no FFT plan for this grid length");
+        const size_t tot = (size_t)T * c.ny * c.nz;
+        for (size_t i = 0; i < tot; ++i)
+            if (c.masks[i] > 1) return fail(T2S_EINVAL, "class " + std::to_string(ci) + ": mask values must be 0 or 1");
+    }
+
+    t2s_plan* plan = new t2s_plan();
+    plan->prm = *p;
+    plan->phi.assign(p->phi, p->phi + T * K);
+    plan->prm.phi = nullptr;
+    plan->hist_len = p->n_outer + 1;
+    const int kk2 = K * (K + 1) / 2;
+    int gbase = 0;
+    for (int ci = 0; ci < n_classes; ++ci) {
+        const t2s_class& src = classes[ci];
+        ClassPlan c;
+        c.ny = src.ny;
+        c.nz = src.nz;
+        c.C = src.ncoils;
+        c.S = src.nslices;
+        c.gbase = gbase;
+        gbase += src.nslices;
+        const int ny = c.ny, nz = c.nz, N = ny * nz;
+        // space-time kernel, FP64, upper triangle, uncentred + transposed, / N
+        std::vector<double> acc((size_t)kk2 * N, 0.0);
+        std::vector<int> cnt(N + 1, 0);
+        int P = 0;
+        for (int t = 0; t < T; ++t)
+            for (int y = 0; y < ny; ++y)
+                for (int z = 0; z < nz; ++z) {
+                    if (!src.masks[((size_t)t * ny + y) * nz + z]) continue;
+                    const int q = ((z + nz / 2) % nz) * ny + (y + ny / 2) % ny;
+                    int tri = 0;
+                    for (int k = 0; k < K; ++k)
+                        for (int l = k; l < K; ++l, ++tri)
+                            acc[(size_t)tri * N + q] += (double)plan->phi[t * K + k] * (double)plan->phi[t * K + l];
+                    cnt[q + 1]++;
+                    ++P;
+                }
+        c.P = P;
+        c.psi.resize((size_t)kk2 * N);
+        for (size_t i = 0; i < c.psi.size(); ++i) c.psi[i] = (float)(acc[i] / (double)N);
+        c.row_ptr.assign(N + 1, 0);
+        for (int q = 0; q < N; ++q) c.row_ptr[q + 1] = c.row_ptr[q] + cnt[q + 1];
+        c.ent_t.assign(std::max(P, 1), 0);
+        c.ent_p.assign(std::max(P, 1), 0);
+        std::vector<int> fillp(c.row_ptr.begin(), c.row_ptr.end() - 1);
+        int pidx = 0;
+        for (int t = 0; t < T; ++t)
+            for (int y = 0; y < ny; ++y)
+                for (int z = 0; z < nz; ++z) {
+                    if (!src.masks[((size_t)t * ny + y) * nz + z]) continue;
+                    const int q = ((z + nz / 2) % nz) * ny + (y + ny / 2) % ny;
+                    const int e = fillp[q]++;
+                    c.ent_t[e] = t;
+                    c.ent_p[e] = pidx++;
+                }
+        roots(ny, c.twy);
+        roots(nz, c.twz);
+        c.npw = (ny / t2s::kRowTile) * K;
+        const size_t kn = (size_t)K * N;
+        c.nrr = (int)std::min<size_t>(256, std::max<size_t>(1, (kn + 4095) / 4096));
+        const int strips = (ny / p->block) * ((nz + 63) / 64);
+        c.nllr = (strips + 3) / 4;
+        c.loaded.assign(c.S, 0);
+        c.outer_run.assign(c.S, 0);
+        c.k_freeze.assign(c.S, -1);
+        c.converged.assign(c.S, 0);
+        plan->cls.push_back(std::move(c));
+    }
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    for (ClassPlan& c : plan->cls) {
+        const size_t N = (size_t)c.ny * c.nz;
+        c.o_psi = take(c.psi.size() * 4);
+        c.o_twy = take((size_t)c.ny * 8);
+        c.o_twz = take((size_t)c.nz * 8);
+        c.o_phi = take((size_t)T * K * 4);
+        c.o_rowptr = take((N + 1) * 4);
+        c.o_entt = take(c.ent_t.size() * 4);
+        c.o_entp = take(c.ent_p.size() * 4);
+        c.o_sens = take((size_t)c.S * c.C * N * 8);
+        c.o_ksp = take((size_t)c.S * c.C * std::max(c.P, 1) * 8);
+        for (int v = 0; v < 7; ++v) c.o_vec[v] = take(vec_bytes(c, K));
+        c.o_tmp = take((size_t)c.S * c.C * K * N * 8);
+        c.o_pw = take((size_t)c.S * c.npw * 8);
+        c.o_rr = take((size_t)c.S * 2 * c.nrr * 8);
+        c.o_g0 = take((size_t)c.S * c.nllr * 8);
+        c.o_llr = take((size_t)c.S * c.nllr * 8 * 8);
+        c.o_hist = take((size_t)c.S * plan->hist_len * 8 * 8);
+        c.o_state = take((size_t)c.S * 2 * 4);
+    }
+    plan->ws_bytes = off;
+    *out = plan;
+    return 0;
+}
+
+int t2s_plan_destroy(t2s_plan* plan) {
+    delete plan;
+    return 0;
+}
+
+int t2s_plan_workspace_bytes(const t2s_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(T2S_EINVAL, "NULL argument");
+    *bytes = plan->ws_bytes;
+    return 0;
+}
+
+int t2s_plan_bind_workspace(t2s_plan* plan, void* dev, size_t bytes, void* stream) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (!dev) return fail(T2S_ENOMEM, "workspace pointer is NULL");
+    if (bytes < plan->ws_bytes)
+        return fail(T2S_ENOMEM, "workspace too small: need " + std::to_string(plan->ws_bytes) + " bytes");
+    if ((uintptr_t)dev % kAlign) return fail(T2S_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    int dev_id = 0, max_lds = 0;
+    HIP_TRY(hipGetDevice(&dev_id));
+    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id));
+    for (const ClassPlan& c : plan->cls) {
+        const size_t need = std::max(t2s::lds_bytes_passA(c.nz), t2s::lds_bytes_passB(c.ny, plan->prm.K)) + 64;
+        if (need > (size_t)max_lds)
+            return fail(T2S_EUNSUPPORTED, "grid needs " + std::to_string(need) + " bytes of LDS per workgroup, device has " +
+                                              std::to_string(max_lds));
+    }
+    plan->ws = (char*)dev;
+    for (ClassPlan& c : plan->cls) {
+        fill_args(plan, c);
+        char* b = plan->ws;
+        HIP_TRY(hipMemcpyAsync(b + c.o_psi, c.psi.data(), c.psi.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(b + c.o_twy, c.twy.data(), c.twy.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(b + c.o_twz, c.twz.data(), c.twz.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(b + c.o_phi, plan->phi.data(), plan->phi.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(b + c.o_rowptr, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(b + c.o_entt, c.ent_t.data(), c.ent_t.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(b + c.o_entp, c.ent_p.data(), c.ent_p.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 0, -1, st));
+        std::fill(c.loaded.begin(), c.loaded.end(), 0);
+    }
+    HIP_TRY(hipStreamSynchronize(st));   // host tables are pageable: finish before returning
+    plan->bound = true;
+    return 0;
+}
+
+int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* sens, const void* ksp, int mem,
+                    void* stream) {
+    if (int e = check_class_index(plan, cls, first, count)) return e;
+    if (!sens || !ksp) return fail(T2S_EINVAL, "sens or ksp is NULL");
+    if (mem != T2S_HOST && mem != T2S_DEVICE) return fail(T2S_EINVAL, "mem must be T2S_HOST or T2S_DEVICE");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    ClassPlan& c = plan->cls[cls];
+    const size_t N = (size_t)c.ny * c.nz;
+    const size_t ns = (size_t)count * c.C * N * 2, nk = (size_t)count * c.C * c.P * 2;
+    if (mem == T2S_HOST) {
+        const float* fs = (const float*)sens;
+        const float* fk = (const float*)ksp;
+        for (size_t i = 0; i < ns; ++i)
+            if (!finite_f(fs[i])) return fail(T2S_ENONFINITE, "coil maps contain NaN/Inf");
+        for (size_t i = 0; i < nk; ++i)
+            if (!finite_f(fk[i])) return fail(T2S_ENONFINITE, "samples contain NaN/Inf");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const hipMemcpyKind kind = mem == T2S_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const ClassArgs& a = c.args;
+    HIP_TRY(hipMemcpyAsync(a.sens + (size_t)first * c.C * N, sens, ns * 4, kind, st));
+    if (nk) HIP_TRY(hipMemcpyAsync(a.ksp + (size_t)first * c.C * c.P, ksp, nk * 4, kind, st));
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, st));
+    HIP_CHECK_LAUNCH(t2s::launch_project(a, first, count, st));
+    HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, st));
+    HIP_CHECK_LAUNCH(t2s::launch_passC(a, first, count, 1, 0.0f, a.b0, 0, st));
+    HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, nullptr, 0, st));
+    if (mem == T2S_HOST) HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i) c.loaded[first + i] = 1;
+    plan->last_stream = st;
+    return 0;
+}
+
+int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* alpha0, int mem, void* stream) {
+    if (int e = check_class_index(plan, cls, first, count)) return e;
+    if (!alpha0) return fail(T2S_EINVAL, "alpha0 is NULL");
+    if (mem != T2S_HOST && mem != T2S_DEVICE) return fail(T2S_EINVAL, "mem must be T2S_HOST or T2S_DEVICE");
+    ClassPlan& c = plan->cls[cls];
+    for (int i = 0; i < count; ++i)
+        if (!c.loaded[first + i]) return fail(T2S_ESTATE, "slice not loaded");
+    const int K = plan->prm.K;
+    const size_t n = (size_t)count * K * c.ny * c.nz * 2;
+    if (mem == T2S_HOST) {
+        const float* f = (const float*)alpha0;
+        for (size_t i = 0; i < n; ++i)
+            if (!finite_f(f[i])) return fail(T2S_ENONFINITE, "alpha0 contains NaN/Inf");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const ClassArgs& a = c.args;
+    float2* xs = a.x + (size_t)first * K * c.ny * c.nz;
+    HIP_TRY(hipMemcpyAsync(xs, alpha0, n * 4, mem == T2S_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, st));
+    // r = b0 + rho z - (A^H A + rho) alpha0 with z = alpha0, u = 0  =>  r = b0 - A^H A alpha0
+    if (int e = run_normal(a, first, count, a.x, 0, 0.0f, a.w, 0, st)) return e;
+    HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, xs, 1, st));
+    if (mem == T2S_HOST) HIP_TRY(hipStreamSynchronize(st));
+    return 0;
+}
+
+int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (mode != T2S_BATCHED && mode != T2S_PER_SLICE) return fail(T2S_EINVAL, "bad mode");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    for (const ClassPlan& c : plan->cls)
+        for (int s = 0; s < c.S; ++s)
+            if (!c.loaded[s]) return fail(T2S_ESTATE, "not every slice is loaded");
+    hipStream_t st = (hipStream_t)stream;
+    plan->last_stream = st;
+    const t2s_params& prm = plan->prm;
+    const bool tolmode = prm.tol > 0;
+    for (ClassPlan& c : plan->cls) {
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, st));
+        std::fill(c.outer_run.begin(), c.outer_run.end(), 0);
+        std::fill(c.k_freeze.begin(), c.k_freeze.end(), -1);
+        std::fill(c.converged.begin(), c.converged.end(), 0);
+    }
+    auto outer_all = [&](int k) -> int {
+        for (ClassPlan& c : plan->cls) {
+            if (mode == T2S_BATCHED) {
+                if (int e = run_outer(plan, c.args, 0, c.S, k, st)) return e;
+            } else {
+                for (int s = 0; s < c.S; ++s)
+                    if (int e = run_outer(plan, c.args, s, 1, k, st)) return e;
+            }
+        }
+        return 0;
+    };
+    int warn = 0;
+    if (!tolmode) {
+        for (int k = 0; k < prm.n_outer; ++k)
+            if (int e = outer_all(k)) return e;
+        for (ClassPlan& c : plan->cls) std::fill(c.outer_run.begin(), c.outer_run.end(), prm.n_outer);
+    } else {
+        // per-slice decisions every check_every outer iterations (see t2s.h)
+        std::vector<std::vector<double>> res(plan->cls.size());
+        std::vector<std::vector<int>> active(plan->cls.size());
+        for (size_t ci = 0; ci < plan->cls.size(); ++ci) active[ci].assign(plan->cls[ci].S, 1);
+        std::vector<double> hbuf;
+        int k = 0;
+        bool any = true;
+        while (k < prm.n_outer && any) {
+            const int kend = std::min(prm.n_outer, k + prm.check_every);
+            for (; k < kend; ++k)
+                if (int e = outer_all(k)) return e;
+            HIP_TRY(hipStreamSynchronize(st));
+            any = false;
+            for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
+                ClassPlan& c = plan->cls[ci];
+                hbuf.resize((size_t)c.S * plan->hist_len * 8);
+                HIP_TRY(hipMemcpy(hbuf.data(), c.args.hist, hbuf.size() * 8, hipMemcpyDeviceToHost));
+                for (int s = 0; s < c.S; ++s) {
+                    if (!active[ci][s]) continue;
+                    c.outer_run[s] = k;
+                    double rp, rd;
+                    const double* h = &hbuf[((size_t)s * plan->hist_len + (k - 1)) * 8];
+                    residuals_from_hist(h, prm.rho, &rp, &rd);
+                    const double r = std::max(rp, rd);
+                    bool stop = false;
+                    if (c.k_freeze[s] >= 0 && r <= prm.tol) {
+                        stop = true;
+                        c.converged[s] = 1;
+                    } else if (c.k_freeze[s] < 0 && k - 1 >= prm.freeze_window) {
+                        double rpo, rdo;
+                        residuals_from_hist(&hbuf[((size_t)s * plan->hist_len + (k - 1 - prm.freeze_window)) * 8],
+                                            prm.rho, &rpo, &rdo);
+                        if (r > (1.0 - prm.freeze_stall) * std::max(rpo, rdo)) {
+                            c.k_freeze[s] = k - 1;
+                            HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 1, k - 1, st));
+                        }
+                    }
+                    if (stop) {
+                        active[ci][s] = 0;
+                        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 0, c.k_freeze[s], st));
+                    } else {
+                        any = true;
+                    }
+                }
+            }
+        }
+        for (size_t ci = 0; ci < plan->cls.size(); ++ci)
+            for (int s = 0; s < plan->cls[ci].S; ++s)
+                if (active[ci][s]) warn = T2S_WNOTCONVERGED;
+    }
+    plan->reconstructed = true;
+    if (warn) return fail(warn, "tolerance not met by n_outer for some slices");
+    return 0;
+}
+
+int t2s_read_coeffs(t2s_plan* plan, int cls, int first, int count, void* out, int which, int mem, void* stream) {
+    if (int e = check_class_index(plan, cls, first, count)) return e;
+    if (!out) return fail(T2S_EINVAL, "out is NULL");
+    if (mem != T2S_HOST && mem != T2S_DEVICE) return fail(T2S_EINVAL, "mem must be T2S_HOST or T2S_DEVICE");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    const ClassPlan& c = plan->cls[cls];
+    const ClassArgs& a = c.args;
+    const float2* src = nullptr;
+    switch (which) {
+        case T2S_ALPHA: src = a.x; break;
+        case T2S_Z: src = a.z; break;
+        case T2S_U: src = a.u; break;
+        case T2S_ADJOINT: src = a.b0; break;
+        default: return fail(T2S_EINVAL, "bad `which`");
+    }
+    const size_t n = (size_t)plan->prm.K * c.ny * c.nz;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(out, src + (size_t)first * n, (size_t)count * n * 8,
+                           mem == T2S_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    if (mem == T2S_HOST) HIP_TRY(hipStreamSynchronize(st));
+    return 0;
+}
+
+int t2s_get_slice_report(const t2s_plan* plan, int cls, int slice, t2s_slice_report* out) {
+    if (int e = check_class_index(plan, cls, slice, 1)) return e;
+    if (!out) return fail(T2S_EINVAL, "out is NULL");
+    if (!plan->reconstructed) return fail(T2S_ESTATE, "no reconstruct has run");
+    const ClassPlan& c = plan->cls[cls];
+    const int k = c.outer_run[slice];
+    out->outer_iterations = k;
+    out->k_freeze = c.k_freeze[slice];
+    out->converged = c.converged[slice];
+    out->r_primal = out->r_dual = std::numeric_limits<double>::quiet_NaN();
+    if (k > 0) {
+        double h[8];
+        HIP_TRY(hipStreamSynchronize(plan->last_stream));
+        HIP_TRY(hipMemcpy(h, c.args.hist + ((size_t)slice * plan->hist_len + (k - 1)) * 8, sizeof(h),
+                          hipMemcpyDeviceToHost));
+        residuals_from_hist(h, plan->prm.rho, &out->r_primal, &out->r_dual);
+    }
+    return 0;
+}
+
+int t2s_apply_normal(t2s_plan* plan, int cls, int first, int count, const void* in, void* out, float rho_add,
+                     void* stream) {
+    if (int e = check_class_index(plan, cls, first, count)) return e;
+    if (!in || !out) return fail(T2S_EINVAL, "in or out is NULL");
+    if (in == out) return fail(T2S_EINVAL, "in and out must not overlap");
+    if (!finite_f(rho_add)) return fail(T2S_ENONFINITE, "rho_add is NaN/Inf");
+    ClassPlan& c = plan->cls[cls];
+    for (int i = 0; i < count; ++i)
+        if (!c.loaded[first + i]) return fail(T2S_ESTATE, "slice not loaded");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, first, count, 1, -1, st));
+    return run_normal(c.args, first, count, (const float2*)in, first, rho_add, (float2*)out, first, st);
+}
+
+int t2s_apply_llr(t2s_plan* plan, int cls, int first, int count, const void* in, void* out, float tau,
+                  const int* shifts, void* stream) {
+    if (int e = check_class_index(plan, cls, first, count)) return e;
+    if (!in || !out || !shifts) return fail(T2S_EINVAL, "NULL argument");
+    if (!finite_f(tau) || tau < 0) return fail(T2S_EINVAL, "tau must be finite and >= 0");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    const int b = plan->prm.block;
+    for (int i = 0; i < count; ++i)
+        if (shifts[2 * i] < 0 || shifts[2 * i] >= b || shifts[2 * i + 1] < 0 || shifts[2 * i + 1] >= b)
+            return fail(T2S_EINVAL, "shift out of [0, block)");
+    const ClassPlan& c = plan->cls[cls];
+    const size_t n = (size_t)plan->prm.K * c.ny * c.nz;
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < count; ++i)
+        HIP_CHECK_LAUNCH(t2s::launch_llr(c.args, first + i, 1, t2s::kLlrProx, 0, (const float2*)in + i * n,
+                                         (float2*)out + i * n, tau, shifts[2 * i], shifts[2 * i + 1], st));
+    return 0;
+}
+
+int t2s_get_psi(const t2s_plan* plan, int cls, float* out) {
+    if (int e = check_class_index(plan, cls, 0, 1)) return e;
+    if (!out) return fail(T2S_EINVAL, "out is NULL");
+    const ClassPlan& c = plan->cls[cls];
+    std::memcpy(out, c.psi.data(), c.psi.size() * 4);
+    return 0;
+}
+
+}  // extern "C"

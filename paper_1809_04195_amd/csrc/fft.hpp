@@ -1,0 +1,347 @@
+// fft.hpp -- mixed-radix complex FFT building blocks for gfx950 (also compilable
+// as plain C++ so the index arithmetic and the codelets can be checked on a CPU).
+//
+// Transforms are unnormalised: forward X[k] = sum_n x[n] W_L^{nk}, W_L = exp(-2 pi i / L);
+// inverse uses W_L^{-nk}.  A length-L transform is a sequence of radix-R Stockham
+// passes (R from the plan of L).  Pass p with stride NS (product of the earlier
+// radices) does, for every butterfly j in [0, L/R):
+//     v[r]  = x[j + r L/R]                      r = 0..R-1
+//     v[r] *= W_{NS R}^{r (j mod NS)}            (skipped when NS == 1)
+//     v     = DFT_R(v)
+//     y[(j / NS) NS R + (j mod NS) + r NS] = v[r]
+// which leaves the result in natural order after the last pass.  Small DFTs run
+// in registers (radix 2/3/4/5 codelets composed by Cooley-Tukey with compile-time
+// twiddles); the inter-pass twiddles W_L^m come from a table (LDS on the GPU).
+#pragma once
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define T2S_HD __host__ __device__
+#define T2S_INL __forceinline__
+#else
+#include <cstdint>
+#define T2S_HD
+#define T2S_INL inline
+struct float2 {
+    float x, y;
+};
+static inline float2 make_float2(float a, float b) { return float2{a, b}; }
+#endif
+
+namespace t2s {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+T2S_HD T2S_INL float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+T2S_HD T2S_INL float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+T2S_HD T2S_INL float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+T2S_HD T2S_INL float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+T2S_HD T2S_INL float2 conjc(float2 a) { return make_float2(a.x, -a.y); }
+T2S_HD T2S_INL float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+T2S_HD T2S_INL float2 mul_minus_i(float2 a) { return make_float2(a.y, -a.x); }   // a * (-i)
+T2S_HD T2S_INL float2 mul_plus_i(float2 a) { return make_float2(-a.y, a.x); }    // a * (+i)
+
+// ---------------------------------------------------------------------------
+// compile-time roots of unity (double precision Taylor series after reduction
+// of the angle into [-pi/2, pi/2])
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x) {
+    double t = x, s = x;
+    for (int i = 1; i < 18; ++i) {
+        t *= -x * x / double((2 * i) * (2 * i + 1));
+        s += t;
+    }
+    return s;
+}
+constexpr double taylor_cos(double x) {
+    double t = 1.0, s = 1.0;
+    for (int i = 1; i < 18; ++i) {
+        t *= -x * x / double((2 * i - 1) * (2 * i));
+        s += t;
+    }
+    return s;
+}
+
+struct cplxd {
+    double re, im;
+};
+
+// exp(-2 pi i m / n)
+constexpr cplxd root_of_unity(long m, long n) {
+    m %= n;
+    if (m < 0) m += n;
+    if ((4 * m) % n == 0) {
+        const long q = (4 * m) / n;  // quarter turns
+        if (q == 0) return cplxd{1.0, 0.0};
+        if (q == 1) return cplxd{0.0, -1.0};
+        if (q == 2) return cplxd{-1.0, 0.0};
+        return cplxd{0.0, 1.0};
+    }
+    double th = (2 * m > n) ? -2.0 * kPi * double(n - m) / double(n) : 2.0 * kPi * double(m) / double(n);
+    double s = 0.0, c = 0.0;
+    if (th > kPi / 2) {
+        const double p = kPi - th;
+        s = taylor_sin(p);
+        c = -taylor_cos(p);
+    } else if (th < -kPi / 2) {
+        const double p = -kPi - th;
+        s = taylor_sin(p);
+        c = -taylor_cos(p);
+    } else {
+        s = taylor_sin(th);
+        c = taylor_cos(th);
+    }
+    return cplxd{c, -s};
+}
+
+template <int R>
+struct RootTable {
+    float re[R];
+    float im[R];
+    constexpr RootTable() : re(), im() {
+        for (int m = 0; m < R; ++m) {
+            const cplxd w = root_of_unity(m, R);
+            re[m] = float(w.re);
+            im[m] = float(w.im);
+        }
+    }
+};
+
+// x * W_R^e for a compile-time-constant (after unrolling) exponent e
+template <int R>
+T2S_HD T2S_INL float2 tw_const(float2 x, int e) {
+    e %= R;
+    if (e == 0) return x;
+    if (4 * e == R) return mul_minus_i(x);
+    if (2 * e == R) return make_float2(-x.x, -x.y);
+    if (4 * e == 3 * R) return mul_plus_i(x);
+    constexpr RootTable<R> T{};
+    return cmul(x, make_float2(T.re[e], T.im[e]));
+}
+
+constexpr int first_factor(int R) {
+    return (R % 4 == 0 && R != 4) ? 4 : (R % 2 == 0 && R != 2) ? 2 : (R % 3 == 0 && R != 3) ? 3 : (R % 5 == 0 && R != 5) ? 5 : R;
+}
+
+// ---------------------------------------------------------------------------
+// forward DFT codelets, in registers
+// ---------------------------------------------------------------------------
+template <int R>
+T2S_HD T2S_INL void dft(float2 (&v)[R]);
+
+template <int R>
+T2S_HD T2S_INL void dft_base(float2 (&v)[R]) {
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+        constexpr float s3 = 0.866025403784438646763723170752936183f;  // sin(2 pi / 3)
+        const float2 t = cadd(v[1], v[2]);
+        const float2 d = csub(v[1], v[2]);
+        const float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
+        const float2 q = make_float2(s3 * d.y, -s3 * d.x);  // -i s3 d
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, q);
+        v[2] = csub(m, q);
+    } else if constexpr (R == 4) {
+        const float2 t0 = cadd(v[0], v[2]);
+        const float2 t1 = csub(v[0], v[2]);
+        const float2 t2 = cadd(v[1], v[3]);
+        const float2 t3 = mul_minus_i(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    } else if constexpr (R == 5) {
+        constexpr float c1 = 0.309016994374947424102293417182819059f;   // cos(2 pi / 5)
+        constexpr float c2 = -0.809016994374947424102293417182819059f;  // cos(4 pi / 5)
+        constexpr float s1 = 0.951056516295153572116439333379382143f;   // sin(2 pi / 5)
+        constexpr float s2 = 0.587785252292473129168705954639072769f;   // sin(4 pi / 5)
+        const float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+        const float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+        const float2 x0 = v[0];
+        const float2 m1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+        const float2 m2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+        const float2 n1 = make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
+        const float2 n2 = make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
+        v[0] = make_float2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+        v[1] = cadd(m1, mul_minus_i(n1));
+        v[4] = cadd(m1, mul_plus_i(n1));
+        v[2] = cadd(m2, mul_minus_i(n2));
+        v[3] = cadd(m2, mul_plus_i(n2));
+    }
+}
+
+// R = A * B: n = B n1 + n2, k = k1 + A k2
+template <int R>
+T2S_HD T2S_INL void dft(float2 (&v)[R]) {
+    constexpr int A = first_factor(R);
+    if constexpr (A == R) {
+        dft_base<R>(v);
+    } else {
+        constexpr int B = R / A;
+        float2 Y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) {
+            float2 a[A];
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) a[n1] = v[B * n1 + n2];
+            dft<A>(a);
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) Y[n2 * A + k1] = tw_const<R>(a[k1], n2 * k1);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            float2 b[B];
+#pragma unroll
+            for (int n2 = 0; n2 < B; ++n2) b[n2] = Y[n2 * A + k1];
+            dft<B>(b);
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = b[k2];
+        }
+    }
+}
+
+template <int R, bool INV>
+T2S_HD T2S_INL void dft_dir(float2 (&v)[R]) {
+    if constexpr (INV) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r].y = -v[r].y;
+        dft<R>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r].y = -v[r].y;
+    } else {
+        dft<R>(v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// radix plans: L = R1 * R2 (* R3)
+// ---------------------------------------------------------------------------
+template <int... Rs>
+struct Radices {};
+
+template <int L>
+struct FftPlan;
+template <> struct FftPlan<16> { using type = Radices<4, 4>; };
+template <> struct FftPlan<32> { using type = Radices<8, 4>; };
+template <> struct FftPlan<48> { using type = Radices<16, 3>; };
+template <> struct FftPlan<64> { using type = Radices<8, 8>; };
+template <> struct FftPlan<96> { using type = Radices<16, 6>; };
+template <> struct FftPlan<128> { using type = Radices<16, 8>; };
+template <> struct FftPlan<160> { using type = Radices<16, 10>; };
+template <> struct FftPlan<192> { using type = Radices<16, 12>; };
+template <> struct FftPlan<256> { using type = Radices<16, 16>; };
+template <> struct FftPlan<320> { using type = Radices<16, 20>; };
+template <> struct FftPlan<384> { using type = Radices<16, 24>; };
+template <> struct FftPlan<512> { using type = Radices<16, 32>; };
+
+constexpr bool fft_length_supported(int L) {
+    return L == 16 || L == 32 || L == 48 || L == 64 || L == 96 || L == 128 || L == 160 || L == 192 ||
+           L == 256 || L == 320 || L == 384 || L == 512;
+}
+
+// padded LDS position of element i of a transform (one spare slot per 16)
+T2S_HD T2S_INL int ph(int i) { return i + (i >> 4); }
+// LDS stride between transforms of length L (odd, so rows start on different banks)
+constexpr int lds_ld(int L) { return (L + L / 16) | 1; }
+
+// one Stockham pass for the items [tid, ntr * L / R) step nthr
+template <int L, int R, int NS, bool INV>
+T2S_HD T2S_INL void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst, int ntr, int ld,
+                                  const float2* __restrict__ tw, int tid, int nthr) {
+    constexpr int NB = L / R;
+    for (int it = tid; it < ntr * NB; it += nthr) {
+        const int t = it / NB;
+        const int j = it - t * NB;
+        const float2* s = src + t * ld;
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = s[ph(j + r * NB)];
+        if constexpr (NS > 1) {
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[(r * k * (L / (NS * R))) % L];
+                if (INV) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+        }
+        dft_dir<R, INV>(v);
+        const int base = (j / NS) * NS * R + (j % NS);
+        float2* d = dst + t * ld;
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[ph(base + r * NS)] = v[r];
+    }
+}
+
+template <typename P>
+struct PassCount;
+template <int... Rs>
+struct PassCount<Radices<Rs...>> {
+    static constexpr int value = sizeof...(Rs);
+};
+
+template <int L>
+constexpr int fft_passes() {
+    return PassCount<typename FftPlan<L>::type>::value;
+}
+
+// Host-side sequential emulation of the LDS FFT (all "threads" of a pass, then the
+// next pass): the same pass code as the device path, used by CPU tests.
+template <int L, int NS, bool INV, int R, int... Rest>
+T2S_INL float2* fft_emulate_passes(float2* a, float2* b, int ntr, int ld, const float2* tw) {
+    stockham_pass<L, R, NS, INV>(a, b, ntr, ld, tw, 0, 1);
+    if constexpr (sizeof...(Rest) > 0) {
+        return fft_emulate_passes<L, NS * R, INV, Rest...>(b, a, ntr, ld, tw);
+    } else {
+        return b;
+    }
+}
+
+template <int L, bool INV, int... Rs>
+T2S_INL float2* fft_emulate_unpack(Radices<Rs...>, float2* a, float2* b, int ntr, int ld, const float2* tw) {
+    return fft_emulate_passes<L, 1, INV, Rs...>(a, b, ntr, ld, tw);
+}
+
+template <int L, bool INV>
+T2S_INL float2* fft_emulate(float2* a, float2* b, int ntr, int ld, const float2* tw) {
+    return fft_emulate_unpack<L, INV>(typename FftPlan<L>::type{}, a, b, ntr, ld, tw);
+}
+
+#if defined(__HIPCC__)
+// Device LDS FFT of ntr transforms, all threads of the workgroup taking part.
+// Input in `a` (padded layout); returns the buffer (a or b) that holds the result.
+// Ends with a barrier, so the result can be read by any thread.
+template <int L, int NS, bool INV, int R, int... Rest>
+__device__ T2S_INL float2* fft_lds_passes(float2* a, float2* b, int ntr, int ld, const float2* tw) {
+    stockham_pass<L, R, NS, INV>(a, b, ntr, ld, tw, threadIdx.x, blockDim.x);
+    __syncthreads();
+    if constexpr (sizeof...(Rest) > 0) {
+        return fft_lds_passes<L, NS * R, INV, Rest...>(b, a, ntr, ld, tw);
+    } else {
+        return b;
+    }
+}
+
+template <int L, bool INV, int... Rs>
+__device__ T2S_INL float2* fft_lds_unpack(Radices<Rs...>, float2* a, float2* b, int ntr, int ld, const float2* tw) {
+    return fft_lds_passes<L, 1, INV, Rs...>(a, b, ntr, ld, tw);
+}
+
+template <int L, bool INV>
+__device__ T2S_INL float2* fft_lds(float2* a, float2* b, int ntr, int ld, const float2* tw) {
+    return fft_lds_unpack<L, INV>(typename FftPlan<L>::type{}, a, b, ntr, ld, tw);
+}
+#endif
+
+}  // namespace t2s

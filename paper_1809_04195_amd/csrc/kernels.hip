@@ -1,0 +1,756 @@
+// kernels.hip -- gfx950 kernels of the T2-Shuffling slice solver.
+//
+// Normal operator M p = S^H F^H Psi F S p + rho p (Sec. IV-B, eqs. commute /
+// normaleq; fused three-pass schedule after Alg. 1):
+//   pass A  (Alg. 1, first panel loop):  per (slice, 16-row tile, k): p = r + beta p
+//           (CG direction update, fused), then for every coil c: S_c p_k and an
+//           nz-point FFT of each row; written transposed ([nz][ny], y contiguous)
+//           so pass B reads whole columns -- the paper's "leave it transposed"
+//           shortcut of Fig. 3 that saves two of four transposes.
+//   pass B  (second loop, with the forward column FFT before Psi that the
+//           printed loop omits): per (slice, coil, column tile): ny-point FFT of
+//           every column of all K coefficient images, the K x K real symmetric
+//           mix Psi(n) at every k-space location, ny-point inverse FFT.
+//   pass C  (third loop): per (slice, 16-row tile, k): inverse nz-point FFT of
+//           the rows of every coil, sum_c conj(S_c) (.), + rho p, and the partial
+//           <p, Mp> of the CG step.
+// The centring of F and the 1/N of the unnormalised FFT pair are folded into the
+// kernel table (uncentred order, / N), so no phase-modulation pass exists.
+//
+// LLR z-step (Sec. II-B eq. llr, blocked form; single pass of Sec. IV-C): one
+// 64-lane wavefront per strip of 64/b blocks; lane = voxel column, b rows per lane;
+// Gram matrix per block by cross-lane sums, complex Jacobi eigen-decomposition in
+// FP64, W = V diag(max(sigma - tau, 0) / sigma) V^H, z = v W, fused with the ADMM
+// u- and residual updates.
+#include <cmath>
+
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace t2s {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double partial_sum(PartialSrc g, int s) {
+    if (g.base == nullptr) return 0.0;
+    const double* q = g.base + (size_t)s * g.stride;
+    double acc = 0.0;
+    for (int i = 0; i < g.count; ++i) acc += q[i];
+    return acc;
+}
+
+// sum over the workgroup (fixed order); result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    return r;
+}
+
+__device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[2 * s] != 0; }
+
+__host__ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// pass A
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(kThreads) void k_passA(ClassArgs a, int s0, const float2* __restrict__ src, int src_s0,
+                                                     int first, PartialSrc gc, PartialSrc gp) {
+    constexpr int RT = kRowTile;
+    constexpr int LD = lds_ld(L);
+    constexpr int EPT = (RT * L + kThreads - 1) / kThreads;
+    extern __shared__ float2 lds[];
+    float2* tw = lds;
+    float2* buf0 = lds + L;
+    float2* buf1 = buf0 + RT * LD;
+
+    const int s = s0 + blockIdx.z;
+    if (!slice_active(a, s)) return;
+    const int k = blockIdx.y;
+    const int y0 = blockIdx.x * RT;
+    const int ny = a.ny;
+    const size_t N = (size_t)ny * L;
+    const int tid = threadIdx.x;
+
+    for (int i = tid; i < L; i += kThreads) tw[i] = a.twz[i];
+
+    float beta = 0.0f;
+    if (!first) {
+        const double g1 = partial_sum(gc, s), g0 = partial_sum(gp, s);
+        beta = g0 > 0.0 ? (float)(g1 / g0) : 0.0f;
+    }
+    const size_t vbase = ((size_t)s * a.K + k) * N + (size_t)y0 * L;
+    const float2* rs = src + ((size_t)(s - src_s0) * a.K + k) * N + (size_t)y0 * L;
+    float2* ps = a.p + vbase;
+    float2 pv[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * kThreads;
+        if (e < RT * L) {
+            float2 v = rs[e];
+            if (!first) {
+                const float2 po = ps[e];
+                v = make_float2(v.x + beta * po.x, v.y + beta * po.y);
+            }
+            ps[e] = v;
+            pv[i] = v;
+        }
+    }
+    for (int c = 0; c < a.C; ++c) {
+        const float2* S = a.sens + ((size_t)s * a.C + c) * N + (size_t)y0 * L;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * kThreads;
+            if (e < RT * L) {
+                const int row = e / L, zc = e - row * L;
+                buf0[row * LD + ph(zc)] = cmul(S[e], pv[i]);
+            }
+        }
+        __syncthreads();
+        const float2* res = fft_lds<L, false>(buf0, buf1, RT, LD, tw);
+        float2* out = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + y0;
+        for (int e = tid; e < RT * L; e += kThreads) {
+            const int row = e % RT, zc = e / RT;
+            out[(size_t)zc * ny + row] = res[row * LD + ph(zc)];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass B
+// ---------------------------------------------------------------------------
+template <int L, int MODE>
+__global__ __launch_bounds__(kThreads) void k_passB(ClassArgs a, int s0, int W) {
+    constexpr int LD = lds_ld(L);
+    extern __shared__ float2 lds[];
+    float2* tw = lds;
+    const int K = a.K;
+    float2* buf0 = lds + L;
+    float2* buf1 = buf0 + K * W * LD;
+
+    const int s = s0 + blockIdx.z;
+    if (!slice_active(a, s)) return;
+    const int c = blockIdx.y;
+    const int z0 = blockIdx.x * W;
+    const int nz = a.nz;
+    const size_t N = (size_t)L * nz;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < L; i += kThreads) tw[i] = a.twy[i];
+
+    float2* base = a.tmp + ((size_t)s * a.C + c) * K * N + (size_t)z0 * L;
+    const int ntr = K * W;
+    for (int e = tid; e < ntr * L; e += kThreads) {
+        const int tr = e / L, i = e - tr * L;
+        const int k = tr / W, w = tr - k * W;
+        buf0[tr * LD + ph(i)] = base[(size_t)k * N + (size_t)w * L + i];
+    }
+    __syncthreads();
+    float2* res;
+    if constexpr (MODE == 0) {
+        float2* f = fft_lds<L, false>(buf0, buf1, ntr, LD, tw);
+        for (int e = tid; e < W * L; e += kThreads) {
+            const int w = e / L, i = e - w * L;
+            const size_t pidx = (size_t)(z0 + w) * L + i;
+            float2 v[kMaxK];
+#pragma unroll
+            for (int kk = 0; kk < kMaxK; ++kk)
+                if (kk < K) v[kk] = f[(kk * W + w) * LD + ph(i)];
+#pragma unroll
+            for (int kk = 0; kk < kMaxK; ++kk) {
+                if (kk < K) {
+                    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int l = 0; l < kMaxK; ++l) {
+                        if (l < K) {
+                            const int lo = kk < l ? kk : l, hi = kk < l ? l : kk;
+                            const int tri = lo * K - (lo * (lo - 1)) / 2 + (hi - lo);
+                            const float q = a.psi[(size_t)tri * N + pidx];
+                            acc.x += q * v[l].x;
+                            acc.y += q * v[l].y;
+                        }
+                    }
+                    f[(kk * W + w) * LD + ph(i)] = acc;
+                }
+            }
+        }
+        __syncthreads();
+        float2* other = (f == buf0) ? buf1 : buf0;
+        res = fft_lds<L, true>(f, other, ntr, LD, tw);
+    } else {
+        res = fft_lds<L, true>(buf0, buf1, ntr, LD, tw);
+    }
+    for (int e = tid; e < ntr * L; e += kThreads) {
+        const int tr = e / L, i = e - tr * L;
+        const int k = tr / W, w = tr - k * W;
+        base[(size_t)k * N + (size_t)w * L + i] = res[tr * LD + ph(i)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass C
+// ---------------------------------------------------------------------------
+template <int L, int MODE>
+__global__ __launch_bounds__(kThreads) void k_passC(ClassArgs a, int s0, float rho_add, float2* __restrict__ outp,
+                                                     int out_s0) {
+    constexpr int RT = kRowTile;
+    constexpr int LD = lds_ld(L);
+    constexpr int EPT = (RT * L + kThreads - 1) / kThreads;
+    extern __shared__ float2 lds[];
+    float2* tw = lds;
+    float2* buf0 = lds + L;
+    float2* buf1 = buf0 + RT * LD;
+    __shared__ double red[kThreads / 64];
+
+    const int s = s0 + blockIdx.z;
+    if (!slice_active(a, s)) return;
+    const int k = blockIdx.y;
+    const int y0 = blockIdx.x * RT;
+    const int ny = a.ny;
+    const size_t N = (size_t)ny * L;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < L; i += kThreads) tw[i] = a.twz[i];
+
+    float2 acc[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) acc[i] = make_float2(0.f, 0.f);
+
+    for (int c = 0; c < a.C; ++c) {
+        const float2* in = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + y0;
+        for (int e = tid; e < RT * L; e += kThreads) {
+            const int row = e % RT, zc = e / RT;
+            buf0[row * LD + ph(zc)] = in[(size_t)zc * ny + row];
+        }
+        __syncthreads();
+        const float2* res = fft_lds<L, true>(buf0, buf1, RT, LD, tw);
+        const float2* S = a.sens + ((size_t)s * a.C + c) * N + (size_t)y0 * L;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * kThreads;
+            if (e < RT * L) {
+                const int row = e / L, zc = e - row * L;
+                const float2 v = cmulc(res[row * LD + ph(zc)], S[e]);
+                acc[i] = cadd(acc[i], v);
+            }
+        }
+        __syncthreads();
+    }
+    const size_t vbase = ((size_t)s * a.K + k) * N + (size_t)y0 * L;
+    float2* out = outp + ((size_t)(s - out_s0) * a.K + k) * N + (size_t)y0 * L;
+    if constexpr (MODE == 0) {
+        const float2* pp = a.p + vbase;
+        double dot = 0.0;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * kThreads;
+            if (e < RT * L) {
+                const float2 pv = pp[e];
+                const float2 w = make_float2(acc[i].x + rho_add * pv.x, acc[i].y + rho_add * pv.y);
+                out[e] = w;
+                dot += (double)pv.x * (double)w.x + (double)pv.y * (double)w.y;
+            }
+        }
+        const double tot = block_sum(dot, red);
+        if (tid == 0) a.pw[(size_t)s * a.npw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    } else {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * kThreads;
+            if (e < RT * L) out[e] = acc[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// projection of the samples onto the basis (adjoint input), uncentred and
+// transposed: tmp[c][k][q], q = z' ny + y', value
+// (-1)^(y'+z') / sqrt(N) * sum_{samples at the centred location of q} phi[t][k] y_c
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_project(ClassArgs a, int s0) {
+    const int s = s0 + blockIdx.z;
+    const int c = blockIdx.y;
+    const int ny = a.ny, nz = a.nz;
+    const int N = ny * nz;
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= N) return;
+    const int K = a.K;
+    const float2* y = a.ksp + ((size_t)s * a.C + c) * a.P;
+    float2 acc[kMaxK];
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) acc[k] = make_float2(0.f, 0.f);
+    const int e0 = a.row_ptr[q], e1 = a.row_ptr[q + 1];
+    for (int e = e0; e < e1; ++e) {
+        const int t = a.ent_t[e];
+        const float2 v = y[a.ent_p[e]];
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+            if (k < K) {
+                const float f = a.phi[t * K + k];
+                acc[k].x += f * v.x;
+                acc[k].y += f * v.y;
+            }
+    }
+    const int yp = q % ny, zp = q / ny;
+    const float sc = (((yp + zp) & 1) ? -1.0f : 1.0f) / sqrtf((float)N);
+    float2* out = a.tmp + ((size_t)s * a.C + c) * K * (size_t)N + q;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+        if (k < K) out[(size_t)k * N] = cscale(acc[k], sc);
+}
+
+// ---------------------------------------------------------------------------
+// CG update: a = gamma / Re<p, w>;  x += a p;  r -= a w;  partial <r, r>
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_cg_update(ClassArgs a, int s0, PartialSrc gc, int out_buf) {
+    __shared__ double red[kThreads / 64];
+    const int s = s0 + blockIdx.z;
+    if (!slice_active(a, s)) return;
+    const double gamma = partial_sum(gc, s);
+    PartialSrc pws{a.pw, a.npw, a.npw};
+    const double pw = partial_sum(pws, s);
+    const float alpha = (gamma > 0.0 && pw > 0.0) ? (float)(gamma / pw) : 0.0f;
+    const size_t n = (size_t)a.K * a.ny * a.nz;
+    const size_t base = (size_t)s * n;
+    float2* x = a.x + base;
+    float2* r = a.r + base;
+    const float2* p = a.p + base;
+    const float2* w = a.w + base;
+    double dot = 0.0;
+    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (size_t)gridDim.x * kThreads) {
+        const float2 pv = p[e], wv = w[e];
+        float2 xv = x[e], rv = r[e];
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        rv.x -= alpha * wv.x;
+        rv.y -= alpha * wv.y;
+        x[e] = xv;
+        r[e] = rv;
+        dot += (double)rv.x * rv.x + (double)rv.y * rv.y;
+    }
+    const double tot = block_sum(dot, red);
+    if (threadIdx.x == 0) a.rr[((size_t)s * 2 + out_buf) * a.nrr + blockIdx.x] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// state initialisation: x = z = alpha0 (or 0), u = 0, r = b0 - (sub_w ? w : 0)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_init(ClassArgs a, int s0, const float2* __restrict__ alpha0, int sub_w) {
+    __shared__ double red[kThreads / 64];
+    const int s = s0 + blockIdx.z;
+    const size_t n = (size_t)a.K * a.ny * a.nz;
+    const size_t base = (size_t)s * n;
+    const float2* a0 = alpha0 ? alpha0 + (size_t)(s - s0) * n : nullptr;
+    double dot = 0.0;
+    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (size_t)gridDim.x * kThreads) {
+        const float2 xv = a0 ? a0[e] : make_float2(0.f, 0.f);
+        float2 rv = a.b0[base + e];
+        if (sub_w) rv = csub(rv, a.w[base + e]);
+        a.x[base + e] = xv;
+        a.z[base + e] = xv;
+        a.u[base + e] = make_float2(0.f, 0.f);
+        a.r[base + e] = rv;
+        dot += (double)rv.x * rv.x + (double)rv.y * rv.y;
+    }
+    const double tot = block_sum(dot, red);
+    if (threadIdx.x == 0) a.g0[(size_t)s * a.nllr + blockIdx.x] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// LLR: complex Hermitian Jacobi (cyclic, FP64) on the K x K Gram matrix
+// ---------------------------------------------------------------------------
+struct cd2 {
+    double x, y;
+};
+__device__ __forceinline__ cd2 dmul(cd2 a, cd2 b) { return cd2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ cd2 dconj(cd2 a) { return cd2{a.x, -a.y}; }
+
+template <int K>
+__device__ __forceinline__ void jacobi_eig(cd2 (&A)[K][K], cd2 (&V)[K][K]) {
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j < K; ++j) V[i][j] = cd2{i == j ? 1.0 : 0.0, 0.0};
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        double off = 0.0, dia = 0.0;
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+            dia += A[p][p].x * A[p][p].x;
+#pragma unroll
+            for (int q = p + 1; q < K; ++q) off += A[p][q].x * A[p][q].x + A[p][q].y * A[p][q].y;
+        }
+        if (off <= 1e-30 * dia || off == 0.0) break;
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < K; ++q) {
+                const cd2 apq = A[p][q];
+                const double g = sqrt(apq.x * apq.x + apq.y * apq.y);
+                if (g == 0.0) continue;
+                const cd2 e = cd2{apq.x / g, apq.y / g};  // phase of a_pq
+                const double th = (A[q][q].x - A[p][p].x) / (2.0 * g);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double sn = t * c;
+                const cd2 ec = dconj(e);
+                // columns p, q:  A <- A J,  J = [[c, sn], [-sn conj(e), c conj(e)]]
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const cd2 aip = A[i][p], aiq = A[i][q];
+                    const cd2 t1 = dmul(ec, aiq);
+                    A[i][p] = cd2{c * aip.x - sn * t1.x, c * aip.y - sn * t1.y};
+                    A[i][q] = cd2{sn * aip.x + c * t1.x, sn * aip.y + c * t1.y};
+                    const cd2 vip = V[i][p], viq = V[i][q];
+                    const cd2 t2 = dmul(ec, viq);
+                    V[i][p] = cd2{c * vip.x - sn * t2.x, c * vip.y - sn * t2.y};
+                    V[i][q] = cd2{sn * vip.x + c * t2.x, sn * vip.y + c * t2.y};
+                }
+                // rows p, q:  A <- J^H A
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const cd2 apj = A[p][j], aqj = A[q][j];
+                    const cd2 t1 = dmul(e, aqj);
+                    A[p][j] = cd2{c * apj.x - sn * t1.x, c * apj.y - sn * t1.y};
+                    A[q][j] = cd2{sn * apj.x + c * t1.x, sn * apj.y + c * t1.y};
+                }
+                A[p][q] = cd2{0.0, 0.0};
+                A[q][p] = cd2{0.0, 0.0};
+                A[p][p].y = 0.0;
+                A[q][q].y = 0.0;
+            }
+        }
+    }
+}
+
+template <int K, int B, int MODE>
+__global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int kouter, const float2* __restrict__ inp,
+                                                   float2* __restrict__ outp, float tau, int sy_arg, int sz_arg) {
+    __shared__ double red[kThreads / 64];
+    const int s = s0 + blockIdx.z;
+    if (MODE == kLlrAdmm && !slice_active(a, s)) return;
+    const int ny = a.ny, nz = a.nz;
+    const size_t N = (size_t)ny * nz;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nsz = (nz + 63) / 64;
+    const int nstrips = (ny / B) * nsz;
+    const int st = blockIdx.x * (kThreads / 64) + wave;
+
+    int sy = sy_arg, sz = sz_arg;
+    if (MODE == kLlrAdmm) {
+        const int fk = a.state[2 * s + 1];
+        const uint64_t kk = (uint64_t)(fk >= 0 ? fk : kouter);
+        const uint64_t h = sm64(sm64(sm64(a.seed) ^ (uint64_t)(a.gbase + s)) ^ kk);
+        sy = (int)((h & 0xFFFFFFFFull) % (uint64_t)B);
+        sz = (int)((h >> 32) % (uint64_t)B);
+    }
+    const size_t vb = (size_t)(MODE == kLlrAdmm ? s : s - s0) * K * N;
+    const bool valid = st < nstrips;
+    const int prow = valid ? st / nsz : 0;
+    const int col = (valid ? (st % nsz) : 0) * 64 + lane;
+    const bool act = valid && col < nz;
+    const int zc = (col + sz) % nz;
+
+    // ---- Gram matrix of this lane's block (FP64) ----
+    cd2 G[K][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int l = 0; l < K; ++l) G[k][l] = cd2{0.0, 0.0};
+    if (act) {
+        for (int i = 0; i < B; ++i) {
+            const int yr = (prow * B + i + sy) % ny;
+            const size_t idx = (size_t)yr * nz + zc;
+            float2 v[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (MODE == kLlrAdmm) v[k] = cadd(a.x[vb + k * N + idx], a.u[vb + k * N + idx]);
+                else v[k] = inp[vb + k * N + idx];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int l = k; l < K; ++l) {
+                    // conj(v_k) v_l
+                    G[k][l].x += (double)v[k].x * v[l].x + (double)v[k].y * v[l].y;
+                    G[k][l].y += (double)v[k].x * v[l].y - (double)v[k].y * v[l].x;
+                }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int l = k; l < K; ++l) {
+#pragma unroll
+            for (int o = 1; o < B; o <<= 1) {
+                G[k][l].x += __shfl_xor(G[k][l].x, o);
+                G[k][l].y += __shfl_xor(G[k][l].y, o);
+            }
+        }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        G[k][k].y = 0.0;
+#pragma unroll
+        for (int l = 0; l < k; ++l) G[k][l] = dconj(G[l][k]);
+    }
+    // ---- eigen-decomposition and shrinkage matrix W = V diag(f) V^H ----
+    cd2 V[K][K];
+    jacobi_eig<K>(G, V);
+    double f[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const double lam = G[i][i].x;
+        const double sg = lam > 0.0 ? sqrt(lam) : 0.0;
+        f[i] = sg > (double)tau ? (sg - (double)tau) / sg : 0.0;
+    }
+    float2 Wm[K][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int l = 0; l < K; ++l) {
+            double wx = 0.0, wy = 0.0;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const cd2 t = dmul(V[k][i], dconj(V[l][i]));
+                wx += f[i] * t.x;
+                wy += f[i] * t.y;
+            }
+            Wm[k][l] = make_float2((float)wx, (float)wy);
+        }
+    // ---- apply: z_l = sum_k v_k W_kl, fused ADMM updates ----
+    double s_az = 0.0, s_zz = 0.0, s_a = 0.0, s_z = 0.0, s_u = 0.0, s_r = 0.0;
+    if (act) {
+        for (int i = 0; i < B; ++i) {
+            const int yr = (prow * B + i + sy) % ny;
+            const size_t idx = vb + (size_t)yr * nz + zc;
+            float2 v[K], xv[K], uv[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (MODE == kLlrAdmm) {
+                    xv[k] = a.x[idx + k * N];
+                    uv[k] = a.u[idx + k * N];
+                    v[k] = cadd(xv[k], uv[k]);
+                } else {
+                    v[k] = inp[idx + k * N];
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < K; ++l) {
+                float2 zl = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int k = 0; k < K; ++k) zl = cadd(zl, cmul(v[k], Wm[k][l]));
+                if (MODE == kLlrAdmm) {
+                    const float2 zo = a.z[idx + l * N];
+                    const float2 rv = a.r[idx + l * N];
+                    const float2 un = csub(v[l], zl);
+                    // r += rho ((z - u_new) - (z_old - u_old))
+                    const float2 d = csub(csub(zl, un), csub(zo, uv[l]));
+                    const float2 rn = make_float2(rv.x + a.rho * d.x, rv.y + a.rho * d.y);
+                    a.z[idx + l * N] = zl;
+                    a.u[idx + l * N] = un;
+                    a.r[idx + l * N] = rn;
+                    const float2 az = csub(xv[l], zl), dz = csub(zl, zo);
+                    s_az += (double)az.x * az.x + (double)az.y * az.y;
+                    s_zz += (double)dz.x * dz.x + (double)dz.y * dz.y;
+                    s_a += (double)xv[l].x * xv[l].x + (double)xv[l].y * xv[l].y;
+                    s_z += (double)zl.x * zl.x + (double)zl.y * zl.y;
+                    s_u += (double)un.x * un.x + (double)un.y * un.y;
+                    s_r += (double)rn.x * rn.x + (double)rn.y * rn.y;
+                } else {
+                    outp[idx + l * N] = zl;
+                }
+            }
+        }
+    }
+    if (MODE == kLlrAdmm) {
+        double sums[6] = {s_az, s_zz, s_a, s_z, s_u, s_r};
+        double* dst = a.llr + ((size_t)s * a.nllr + blockIdx.x) * 8;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const double t = block_sum(sums[j], red);
+            if (threadIdx.x == 0) {
+                dst[j] = t;
+                if (j == 5) a.g0[(size_t)s * a.nllr + blockIdx.x] = t;
+            }
+        }
+    }
+}
+
+__global__ void k_llr_finalize(ClassArgs a, int s0, int k) {
+    const int s = s0 + blockIdx.x;
+    if (!slice_active(a, s)) return;
+    const int j = threadIdx.x;
+    if (j >= 6) return;
+    double acc = 0.0;
+    for (int i = 0; i < a.nllr; ++i) acc += a.llr[((size_t)s * a.nllr + i) * 8 + j];
+    a.hist[((size_t)s * a.hist_len + k) * 8 + j] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+bool fft_supported(int L) { return fft_length_supported(L); }
+
+static size_t lds_rows(int L) { return (size_t)(L + 2 * kRowTile * lds_ld(L)) * sizeof(float2); }
+
+size_t lds_bytes_passA(int nz) { return lds_rows(nz); }
+
+int passB_columns(int ny, int K) {
+    // columns per workgroup: as many as fit 64 KiB of ping-pong LDS, at most 4
+    int W = 4;
+    while (W > 1 && (size_t)(ny + 2 * K * W * lds_ld(ny)) * sizeof(float2) > 65536) W >>= 1;
+    return W;
+}
+
+size_t lds_bytes_passB(int ny, int K) {
+    const int W = passB_columns(ny, K);
+    return (size_t)(ny + 2 * K * W * lds_ld(ny)) * sizeof(float2);
+}
+
+#define T2S_FOR_LENGTHS(X) X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+
+hipError_t launch_passA(const ClassArgs& a, int s0, int count, const float2* src, int src_s0, int first,
+                        PartialSrc gc, PartialSrc gp, hipStream_t st) {
+    const dim3 grid(a.ny / kRowTile, a.K, count);
+    const size_t lds = lds_bytes_passA(a.nz);
+    switch (a.nz) {
+#define X(L)                                                                                   \
+    case L:                                                                                    \
+        hipLaunchKernelGGL(k_passA<L>, grid, dim3(kThreads), lds, st, a, s0, src, src_s0, first, gc, gp); \
+        break;
+        T2S_FOR_LENGTHS(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, hipStream_t st) {
+    const int W = passB_columns(a.ny, a.K);
+    const dim3 grid(a.nz / W, a.C, count);
+    const size_t lds = lds_bytes_passB(a.ny, a.K);
+    switch (a.ny) {
+#define X(L)                                                                                 \
+    case L:                                                                                  \
+        if (mode == 0)                                                                       \
+            hipLaunchKernelGGL((k_passB<L, 0>), grid, dim3(kThreads), lds, st, a, s0, W);    \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_passB<L, 1>), grid, dim3(kThreads), lds, st, a, s0, W);    \
+        break;
+        T2S_FOR_LENGTHS(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float rho_add, float2* out,
+                        int out_s0, hipStream_t st) {
+    const dim3 grid(a.ny / kRowTile, a.K, count);
+    const size_t lds = lds_bytes_passA(a.nz);
+    switch (a.nz) {
+#define X(L)                                                                                          \
+    case L:                                                                                           \
+        if (mode == 0)                                                                                \
+            hipLaunchKernelGGL((k_passC<L, 0>), grid, dim3(kThreads), lds, st, a, s0, rho_add, out, out_s0);  \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_passC<L, 1>), grid, dim3(kThreads), lds, st, a, s0, rho_add, out, out_s0);  \
+        break;
+        T2S_FOR_LENGTHS(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const ClassArgs& a, int s0, int count, hipStream_t st) {
+    const int N = a.ny * a.nz;
+    const dim3 grid((N + kThreads - 1) / kThreads, a.C, count);
+    hipLaunchKernelGGL(k_project, grid, dim3(kThreads), 0, st, a, s0);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st) {
+    const dim3 grid(a.nrr, 1, count);
+    hipLaunchKernelGGL(k_cg_update, grid, dim3(kThreads), 0, st, a, s0, gc, out_buf);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alpha0, int sub_w, hipStream_t st) {
+    const dim3 grid(a.nllr, 1, count);
+    hipLaunchKernelGGL(k_init, grid, dim3(kThreads), 0, st, a, s0, alpha0, sub_w);
+    return hipGetLastError();
+}
+
+template <int K, int B>
+static void launch_llr_kb(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
+                          float tau, int sy, int sz, hipStream_t st) {
+    const dim3 grid(a.nllr, 1, count);
+    if (mode == kLlrAdmm)
+        hipLaunchKernelGGL((k_llr<K, B, kLlrAdmm>), grid, dim3(kThreads), 0, st, a, s0, k, in, out, tau, sy, sz);
+    else
+        hipLaunchKernelGGL((k_llr<K, B, kLlrProx>), grid, dim3(kThreads), 0, st, a, s0, k, in, out, tau, sy, sz);
+}
+
+template <int B>
+static hipError_t launch_llr_b(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in,
+                               float2* out, float tau, int sy, int sz, hipStream_t st) {
+    switch (a.K) {
+        case 1: launch_llr_kb<1, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        case 2: launch_llr_kb<2, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        case 3: launch_llr_kb<3, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        case 4: launch_llr_kb<4, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        case 5: launch_llr_kb<5, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        case 6: launch_llr_kb<6, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        case 7: launch_llr_kb<7, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        case 8: launch_llr_kb<8, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
+                      float tau, int sy, int sz, hipStream_t st) {
+    switch (a.block) {
+        case 4: return launch_llr_b<4>(a, s0, count, mode, k, in, out, tau, sy, sz, st);
+        case 8: return launch_llr_b<8>(a, s0, count, mode, k, in, out, tau, sy, sz, st);
+        case 16: return launch_llr_b<16>(a, s0, count, mode, k, in, out, tau, sy, sz, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+__global__ void k_set_state(ClassArgs a, int s0, int count, int active, int frozen) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        a.state[2 * (s0 + i)] = active;
+        a.state[2 * (s0 + i) + 1] = frozen;
+    }
+}
+
+hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_state, dim3((count + 63) / 64), dim3(64), 0, st, a, s0, count, active, frozen);
+    return hipGetLastError();
+}
+
+hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, int k, hipStream_t st) {
+    hipLaunchKernelGGL(k_llr_finalize, dim3(count), dim3(64), 0, st, a, s0, k);
+    return hipGetLastError();
+}
+
+}  // namespace t2s

@@ -1,0 +1,86 @@
+// kernels.hpp -- device-side data description and launchers of the T2-Shuffling
+// slice solver kernels (gfx950).  Shared by kernels.hip and api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace t2s {
+
+constexpr int kThreads = 256;   // threads per workgroup of every kernel
+constexpr int kRowTile = 16;    // rows per workgroup of the row-FFT passes
+constexpr int kMaxK = 8;
+
+// Sum of `count` per-workgroup partial sums of slice s, in a fixed order.
+struct PartialSrc {
+    const double* base;  // slice s at base + s * stride (nullptr: the sum is 0)
+    int stride;
+    int count;
+};
+
+// Device view of one shape class (all slices of the class in one allocation).
+struct ClassArgs {
+    int ny, nz, C, K, T, P;      // grid, coils, subspace, echoes, samples per coil
+    int npw, nrr, nllr;          // partial-sum counts per slice (pass C, CG update, LLR)
+    int gbase;                   // global index of the class's slice 0
+    int hist_len;                // outer-iteration capacity of the residual history
+    int block;                   // LLR block edge
+    float tau, rho;              // LLR threshold lambda / rho, ADMM penalty
+    uint64_t seed;
+    const float* psi;            // [K(K+1)/2][nz][ny]: upper triangle, uncentred, / (ny nz)
+    const float2* twy;           // W_ny^m, m < ny
+    const float2* twz;           // W_nz^m, m < nz
+    const float* phi;            // [T][K]
+    const int* row_ptr;          // [ny nz + 1] over uncentred transposed positions q = z' ny + y'
+    const int* ent_t;            // echo of each sample entry
+    const int* ent_p;            // sample index (within a coil's P) of each entry
+    float2* sens;                // [S][C][ny][nz]
+    float2* ksp;                 // [S][C][P]
+    float2 *b0, *x, *r, *p, *w, *z, *u;   // [S][K][ny][nz]
+    float2* tmp;                 // [S][C][K][nz][ny]  pass intermediate (k-space, transposed)
+    double* pw;                  // [S][npw]
+    double* rr;                  // [S][2][nrr]
+    double* g0;                  // [S][nllr]   <r, r> at the start of an outer iteration
+    double* llr;                 // [S][nllr][8] residual partial sums of the z-step
+    double* hist;                // [S][hist_len][8] per-outer residual sums
+    int* state;                  // [S][2]: active flag, frozen outer index (-1: none)
+};
+
+// LLR kernel flavours
+enum LlrMode { kLlrAdmm = 0, kLlrProx = 1 };
+
+// ---- launchers (return hipSuccess or the launch error) ----
+// s0/count: slices [s0, s0 + count) of the class.
+
+// p = first ? src : r + beta p (beta from gc / gp); tmp[c][k] = FFT_z(S_c p_k), transposed
+// (src holds slices [src_s0, ...): slice s reads src + (s - src_s0) K N)
+hipError_t launch_passA(const ClassArgs& a, int s0, int count, const float2* src, int src_s0, int first,
+                        PartialSrc gc, PartialSrc gp, hipStream_t st);
+// mode 0: column FFT, Psi mix, column IFFT (in place on tmp); mode 1: column IFFT only
+hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, hipStream_t st);
+// mode 0: out = sum_c conj(S_c) IFFT_z(tmp) + rho_add p, partial <p, out> into pw
+// mode 1: out = sum_c conj(S_c) IFFT_z(tmp)
+// (out holds slices [out_s0, ...))
+hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float rho_add, float2* out,
+                        int out_s0, hipStream_t st);
+// tmp[c][k] = projected, sign-modulated, uncentred k-space of the samples (adjoint input)
+hipError_t launch_project(const ClassArgs& a, int s0, int count, hipStream_t st);
+// x += a p, r -= a w with a = gamma / <p, w>; partial <r, r> into rr[out_buf]
+hipError_t launch_cg_update(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st);
+// x = z = alpha0 (or 0), u = 0, r = b0 - (sub_w ? w : 0); partial <r, r> into g0
+hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alpha0, int sub_w, hipStream_t st);
+// ADMM z/u/r update with the shift of outer iteration k (mode kLlrAdmm), or
+// out = prox(in) at explicit shift (mode kLlrProx)
+hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
+                      float tau, int sy, int sz, hipStream_t st);
+// state[s] = (active, frozen) for slices [s0, s0 + count)
+hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, hipStream_t st);
+// hist[s][k] = sum of the LLR partials of slice s
+hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, int k, hipStream_t st);
+
+bool fft_supported(int L);
+size_t lds_bytes_passA(int nz);
+size_t lds_bytes_passB(int ny, int K);
+int passB_columns(int ny, int K);
+
+}  // namespace t2s

@@ -1,0 +1,171 @@
+"""C-ABI checks that need no GPU: library loads, exports every declared symbol,
+validates arguments before any HIP call, and its host-side plan tables (space-time
+kernel, block-shift schedule) agree with the oracle."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1809_04195_amd as T
+from oracle import t2s as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.skipif(not os.path.exists(T.LIB_PATH), reason="libt2s.so not built")
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "t2s.h")).read()
+    return sorted(set(re.findall(r"\b(t2s_\w+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", T.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (t2s_\w+)", out))
+    declared = header_symbols()
+    assert declared, "no declarations parsed"
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    # the binding wraps every declared entry point
+    assert set(declared) <= set(T.EXPORTED)
+    assert T.t2s_version() >= 100
+
+
+def _classes(ny=32, nz=48, C=2, S=1, T_=6, seed=0):
+    rng = np.random.default_rng(seed)
+    masks = (rng.random((T_, ny, nz)) < 0.3).astype(np.uint8)
+    return [(ny, nz, C, S, masks)], masks
+
+
+def _phi(T_=6, K=3):
+    q, _ = np.linalg.qr(np.random.default_rng(1).standard_normal((T_, K)))
+    return q.astype(np.float32)
+
+
+def _create(phi, cls, **kw):
+    p = T.make_params(phi, kw.pop("lam", 0.01), kw.pop("rho", 0.1), **kw)
+    arr, keep = T.make_classes(cls)
+    h = ctypes.c_void_p()
+    code = T.lib().t2s_plan_create(ctypes.byref(p), arr, len(cls), ctypes.byref(h))
+    return code, h
+
+
+@pytest.mark.parametrize("case,expected", [
+    ("k_too_big", T.T2S_ESHAPE),
+    ("k_gt_t", T.T2S_ESHAPE),
+    ("odd_grid", T.T2S_ESHAPE),
+    ("unsupported_len", T.T2S_EUNSUPPORTED),
+    ("nan_phi", T.T2S_ENONFINITE),
+    ("bad_block", T.T2S_EINVAL),
+    ("bad_rho", T.T2S_EINVAL),
+    ("bad_mask", T.T2S_EINVAL),
+    ("zero_coils", T.T2S_ESHAPE),
+    ("tol_without_window", T.T2S_EINVAL),
+])
+def test_plan_create_rejects(case, expected):
+    phi = _phi()
+    cls, masks = _classes()
+    kw = {}
+    if case == "k_too_big":
+        phi = np.ones((12, 9), np.float32)
+        cls = [(32, 48, 2, 1, np.ones((12, 32, 48), np.uint8))]
+    elif case == "k_gt_t":
+        phi = np.ones((2, 3), np.float32)
+        cls = [(32, 48, 2, 1, np.ones((2, 32, 48), np.uint8))]
+    elif case == "odd_grid":
+        cls = [(40, 48, 2, 1, np.ones((6, 40, 48), np.uint8))]
+    elif case == "unsupported_len":
+        cls = [(112, 48, 2, 1, np.ones((6, 112, 48), np.uint8))]
+    elif case == "nan_phi":
+        phi = phi.copy()
+        phi[2, 1] = np.nan
+    elif case == "bad_block":
+        kw["block"] = 6
+    elif case == "bad_rho":
+        kw["rho"] = 0.0
+    elif case == "bad_mask":
+        m = masks.copy()
+        m[0, 0, 0] = 3
+        cls = [(32, 48, 2, 1, m)]
+    elif case == "zero_coils":
+        cls = [(32, 48, 0, 1, masks)]
+    elif case == "tol_without_window":
+        kw.update(tol=1e-4, freeze_window=0)
+    code, h = _create(phi, cls, **kw)
+    assert code == expected, (code, T.t2s_last_error())
+    assert T.t2s_last_error()
+
+
+def test_null_arguments():
+    L = T.lib()
+    h = ctypes.c_void_p()
+    assert L.t2s_plan_create(None, None, 0, ctypes.byref(h)) == T.T2S_EINVAL
+    assert L.t2s_plan_create(None, None, 0, None) == T.T2S_EINVAL
+    assert L.t2s_reconstruct(None, 0, None) == T.T2S_EINVAL
+    assert L.t2s_load_slices(None, 0, 0, 1, None, None, 0, None) == T.T2S_EINVAL
+
+
+def test_plan_state_errors_without_gpu():
+    phi = _phi()
+    cls, masks = _classes()
+    code, h = _create(phi, cls)
+    assert code == 0
+    L = T.lib()
+    n = ctypes.c_size_t()
+    assert L.t2s_plan_workspace_bytes(h, ctypes.byref(n)) == 0 and n.value > 0
+    # not bound yet: state errors, before any HIP call
+    buf = np.zeros(10, np.complex64)
+    assert L.t2s_load_slices(h, 0, 0, 1, buf.ctypes.data, buf.ctypes.data, 0, None) == T.T2S_ESTATE
+    assert L.t2s_reconstruct(h, 0, None) == T.T2S_ESTATE
+    # bad binds
+    assert L.t2s_plan_bind_workspace(h, None, n.value, None) == T.T2S_ENOMEM
+    assert L.t2s_plan_bind_workspace(h, ctypes.c_void_p(4096), n.value - 1, None) == T.T2S_ENOMEM
+    # bad slice range / class / enum
+    assert L.t2s_load_slices(h, 1, 0, 1, buf.ctypes.data, buf.ctypes.data, 0, None) == T.T2S_EINVAL
+    assert L.t2s_load_slices(h, 0, 0, 2, buf.ctypes.data, buf.ctypes.data, 0, None) == T.T2S_EINVAL
+    assert L.t2s_reconstruct(h, 7, None) == T.T2S_EINVAL
+    rep = T.t2s_slice_report()
+    assert L.t2s_get_slice_report(h, 0, 0, ctypes.byref(rep)) == T.T2S_ESTATE
+    assert L.t2s_plan_destroy(h) == 0
+
+
+def test_psi_table_matches_oracle():
+    phi = _phi(T_=7, K=3)
+    ny, nz = 32, 48
+    masks = (np.random.default_rng(3).random((7, ny, nz)) < 0.4).astype(np.uint8)
+    code, h = _create(phi, [(ny, nz, 2, 1, masks)])
+    assert code == 0
+    got = T.t2s_get_psi(h, 0, 3, ny, nz)                            # [tri][z'][y']
+    psi = O.space_time_kernel(phi.astype(np.float64), masks.astype(bool))  # [K][K][y][z] centred
+    tri = 0
+    for k in range(3):
+        for l in range(k, 3):
+            ref = np.fft.ifftshift(psi[k, l]).T / (ny * nz)          # uncentred, transposed, / N
+            assert np.allclose(got[tri], ref, rtol=1e-6, atol=1e-9), (k, l)
+            tri += 1
+    T.t2s_plan_destroy(h)
+
+
+def test_block_shift_matches_oracle():
+    for seed in (0, 1, 12345, 2**63 + 7):
+        for g in (0, 1, 17, 319):
+            for k in (0, 1, 2, 99, 499):
+                for b in (4, 8, 16):
+                    assert T.t2s_block_shift(seed, g, k, b) == O.block_shift(seed, g, k, b)
+
+
+def test_host_inputs_nonfinite_rejected_before_gpu():
+    # load_slices checks host data before touching the device; use an unbound plan
+    # whose state check comes later than the finiteness check? No: state is first.
+    # So bind is required; this is covered by the GPU tests.  Here: set_initial on an
+    # unloaded slice is a state error.
+    phi = _phi()
+    cls, masks = _classes()
+    code, h = _create(phi, cls)
+    a0 = np.zeros((1, 3, 32, 48), np.complex64)
+    assert T.lib().t2s_set_initial(h, 0, 0, 1, a0.ctypes.data, 0, None) == T.T2S_ESTATE
+    T.t2s_plan_destroy(h)

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: single operator applications are FP32 FFT chains, checked at 1e-5
+relative L2; whole ADMM runs at the 1e-4 relative L2 the build targets on the
+subspace coefficients.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1809_04195_amd as T
+from oracle import t2s as O
+from gpu_helpers import crandn, random_problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(phi, classes, **kw):
+    return T.Plan(phi, classes, **kw)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu(gpu):
+    return gpu
+
+
+OPS_SHAPES = [
+    (64, 64, 4, 16, 3),
+    (32, 16, 2, 6, 2),
+    (48, 96, 3, 10, 4),
+    (192, 320, 6, 20, 5),
+    (256, 256, 8, 80, 4),
+]
+
+
+@pytest.mark.parametrize("ny,nz,C,Tn,K", OPS_SHAPES)
+def test_normal_operator_and_adjoint(ny, nz, C, Tn, K):
+    import torch
+    _say(f"normal/adjoint parity ny={ny} nz={nz} C={C} T={Tn} K={K}")
+    S = 2
+    phi, sens, masks, ksp = random_problem(ny * 7 + nz, ny, nz, C, Tn, K, S=S)
+    plan = _plan(phi, [dict(ny=ny, nz=nz, ncoils=C, nslices=S, masks=masks)], lam=0.01, rho=0.1)
+    plan.load(0, 0, sens, ksp)
+    rng = np.random.default_rng(5)
+    a = crandn(rng, S, K, ny, nz)
+    a_d = torch.from_numpy(a).cuda()
+    out = torch.empty_like(a_d)
+    T.t2s_apply_normal(plan.handle, 0, 0, S, a_d, out, 0.1)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    b0 = plan.read(0, 0, S, T.T2S_ADJOINT)
+    m = masks.astype(bool)
+    psi = O.space_time_kernel(phi, m)
+    for s in range(S):
+        ref = O.normal_psi(a[s], sens[s], psi) + 0.1 * a[s].astype(np.complex128)
+        e = rel(got[s], ref)
+        assert e < 1e-5, f"normal op slice {s}: {e}"
+        refb = O.adjoint(ksp[s], sens[s], phi, m)
+        eb = rel(b0[s], refb)
+        assert eb < 1e-5, f"adjoint slice {s}: {eb}"
+    plan.close()
+
+
+@pytest.mark.parametrize("K,b", [(1, 8), (2, 4), (3, 8), (4, 8), (5, 8), (4, 16), (3, 4)])
+def test_llr_prox(K, b):
+    import torch
+    _say(f"llr prox parity K={K} b={b}")
+    ny, nz = 64, 128 if b != 16 else 64
+    phi, sens, masks, ksp = random_problem(3, ny, nz, 1, max(K, 2), K, S=2)
+    plan = _plan(phi, [dict(ny=ny, nz=nz, ncoils=1, nslices=2, masks=masks)], lam=0.01, rho=0.1, block=b)
+    rng = np.random.default_rng(K * 10 + b)
+    # low-rank-ish blocks plus noise so thresholds hit the spectrum in the middle
+    base = crandn(rng, 2, 1, ny, nz) * crandn(rng, 2, K, 1, 1)
+    v = (base + 0.3 * crandn(rng, 2, K, ny, nz)).astype(np.complex64)
+    tau = 0.9 * b / 8
+    shifts = [(3 % b, 5 % b), (b - 1, 0)]
+    vd = torch.from_numpy(v).cuda()
+    out = torch.empty_like(vd)
+    T.t2s_apply_llr(plan.handle, 0, 0, 2, vd, out, tau, shifts)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for s in range(2):
+        ref = O.llr_prox(v[s], tau, shifts[s], b)
+        e = rel(got[s], ref)
+        assert e < 1e-5, (s, e)
+    # tau = 0 is the identity
+    T.t2s_apply_llr(plan.handle, 0, 0, 2, vd, out, 0.0, shifts)
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), v) < 1e-6
+    plan.close()
+
+
+def _cfg0():
+    from synth import make_config
+    d = make_config(0)
+    return d["cfg"], d["phi"], d["classes"][0]
+
+
+def test_admm_cfg0_parity():
+    _say("ADMM parity: 64x64 C4 T16 K3, 20 outer x 5 CG, seed 0")
+    cfg, phi, cl = _cfg0()
+    plan = _plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=1, masks=cl.masks)],
+                 lam=cfg["lam"], rho=cfg["rho"], block=cfg["block"], n_outer=cfg["n_outer"], n_cg=cfg["n_cg"],
+                 seed=cfg["seed"])
+    plan.load(0, 0, cl.sens, cl.ksp)
+    plan.reconstruct()
+    alpha = plan.read(0, 0, 1)[0]
+    z = plan.read(0, 0, 1, T.T2S_Z)[0]
+    ref = O.admm(cl.ksp[0], cl.sens[0], phi, cl.masks.astype(bool), cfg["lam"], cfg["rho"], cfg["block"],
+                 cfg["n_outer"], cfg["n_cg"], cfg["seed"], g=0)
+    e = rel(alpha, ref.alpha)
+    ez = rel(z, ref.z)
+    _say(f"  rel L2 alpha {e:.3e}  z {ez:.3e}")
+    assert e < 1e-4 and ez < 1e-4
+    rep = plan.report(0, 0)
+    h = ref.history[-1]
+    assert rep["outer_iterations"] == cfg["n_outer"]
+    assert abs(rep["r_primal"] - h["r_primal"]) <= 1e-3 * h["r_primal"] + 1e-7
+    assert abs(rep["r_dual"] - h["r_dual"]) <= 1e-3 * h["r_dual"] + 1e-7
+    plan.close()
+
+
+def test_batched_equals_per_slice_bitwise():
+    _say("batched vs per-slice launches, 3 slices 64x64")
+    phi, sens, masks, ksp = random_problem(11, 64, 64, 3, 8, 3, S=3, frac=0.3)
+    outs = []
+    for mode in (T.T2S_BATCHED, T.T2S_PER_SLICE):
+        plan = _plan(phi, [dict(ny=64, nz=64, ncoils=3, nslices=3, masks=masks)], lam=0.05, rho=0.1,
+                     n_outer=4, n_cg=3, seed=9)
+        plan.load(0, 0, sens, ksp)
+        plan.reconstruct(mode)
+        outs.append(plan.read(0, 0, 3))
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_multiclass_parity():
+    _say("two shape classes in one plan (64x64 C4, 32x48 C2), 2 slices each")
+    phiA, sA, mA, kA = random_problem(21, 64, 64, 4, 8, 3, S=2, frac=0.25)
+    _, sB, mB, kB = random_problem(22, 32, 48, 2, 8, 3, S=2, frac=0.25)
+    # same basis for both classes (plan-wide)
+    kB = kB  # samples are plain inputs
+    plan = _plan(phiA, [dict(ny=64, nz=64, ncoils=4, nslices=2, masks=mA),
+                        dict(ny=32, nz=48, ncoils=2, nslices=2, masks=mB)],
+                 lam=0.02, rho=0.1, n_outer=6, n_cg=4, seed=3)
+    plan.load(0, 0, sA, kA)
+    plan.load(1, 0, sB, kB)
+    plan.reconstruct()
+    for ci, (sens, masks, ksp) in enumerate([(sA, mA, kA), (sB, mB, kB)]):
+        got = plan.read(ci, 0, 2)
+        for s in range(2):
+            g = ci * 2 + s
+            ref = O.admm(ksp[s], sens[s], phiA, masks.astype(bool), 0.02, 0.1, 8, 6, 4, 3, g=g)
+            e = rel(got[s], ref.alpha)
+            assert e < 1e-4, (ci, s, e)
+    plan.close()
+
+
+def test_warm_start_parity():
+    _say("warm start (set_initial) parity, 64x64 C4 K3")
+    cfg, phi, cl = _cfg0()
+    rng = np.random.default_rng(2)
+    m = cl.masks.astype(bool)
+    b0 = O.adjoint(cl.ksp[0], cl.sens[0], phi, m)
+    a0 = (1.5 * b0 + 0.01 * crandn(rng, *b0.shape)).astype(np.complex64)
+    plan = _plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=1, masks=cl.masks)],
+                 lam=cfg["lam"], rho=cfg["rho"], n_outer=8, n_cg=5, seed=cfg["seed"])
+    plan.load(0, 0, cl.sens, cl.ksp)
+    plan.set_initial(0, 0, a0[None])
+    plan.reconstruct()
+    got = plan.read(0, 0, 1)[0]
+    ref = O.admm(cl.ksp[0], cl.sens[0], phi, m, cfg["lam"], cfg["rho"], 8, 8, 5, cfg["seed"], g=0, alpha0=a0)
+    e = rel(got, ref.alpha)
+    assert e < 1e-4, e
+    plan.close()
+
+
+def test_tolerance_mode_replay_parity():
+    _say("tolerance mode: GPU decisions replayed by the oracle, 64x64 C4 K3")
+    cfg, phi, cl = _cfg0()
+    m = cl.masks.astype(bool)
+    plan = _plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=1, masks=cl.masks)],
+                 lam=cfg["lam"], rho=cfg["rho"], n_outer=300, n_cg=5, seed=cfg["seed"], tol=1e-4,
+                 freeze_window=5, freeze_stall=0.05, check_every=5)
+    plan.load(0, 0, cl.sens, cl.ksp)
+    code = plan.reconstruct()
+    rep = plan.report(0, 0)
+    _say(f"  GPU: code {code} outer {rep['outer_iterations']} k_freeze {rep['k_freeze']} "
+         f"r_p {rep['r_primal']:.3e} r_d {rep['r_dual']:.3e}")
+    got = plan.read(0, 0, 1)[0]
+    ref = O.admm(cl.ksp[0], cl.sens[0], phi, m, cfg["lam"], cfg["rho"], 8, 300, 5, cfg["seed"], g=0,
+                 replay=(rep["k_freeze"], rep["outer_iterations"]))
+    e = rel(got, ref.alpha)
+    _say(f"  replay rel L2 {e:.3e}")
+    assert e < 1e-4
+    if code == T.T2S_OK:
+        assert rep["converged"] == 1 and max(rep["r_primal"], rep["r_dual"]) <= 1e-4
+    own = O.admm(cl.ksp[0], cl.sens[0], phi, m, cfg["lam"], cfg["rho"], 8, 300, 5, cfg["seed"], g=0, tol=1e-4,
+                 check_every=5)
+    _say(f"  oracle's own decisions: k_freeze {own.k_freeze} outer {own.n_outer}")
+    plan.close()
+
+
+def test_nonfinite_host_input_rejected():
+    phi, sens, masks, ksp = random_problem(4, 32, 32, 2, 4, 2, S=1)
+    plan = _plan(phi, [dict(ny=32, nz=32, ncoils=2, nslices=1, masks=masks)], lam=0.01, rho=0.1)
+    bad = ksp.copy()
+    bad[0, 0, 3] = np.nan
+    with pytest.raises(T.T2SError) as ei:
+        plan.load(0, 0, sens, bad)
+    assert ei.value.code == T.T2S_ENONFINITE
+    plan.close()
