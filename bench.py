@@ -1,0 +1,235 @@
+"""Throughput of the T2-Shuffling slice reconstruction on one MI355X.
+
+Workload (default): the 320-slice 256 x 256 volume, C = 8 coils, T = 80 echoes,
+K = 4, 1.5 % VD Poisson-disc sampling per echo, 8 x 8 LLR blocks, lambda = 0.01,
+rho = 0.1, 100 ADMM outer x 5 CG iterations, synthetic (seeded) data.
+
+One step = the whole hot path over the volume: projection + adjoint of the
+device-resident samples (t2s_load_slices) and the full ADMM solve
+(t2s_reconstruct), all slices batched per launch.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "readout slices/s & s/volume at equal ADMM residual: plain vs batched+warm-start"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic bytes per slice of each kernel family (one launch covers all slices)
+# ---------------------------------------------------------------------------
+
+
+def alg_bytes_per_slice(kind, ny, nz, C, K, n_cg):
+    N = ny * nz
+    c8 = 8.0 * N
+    if kind == "pass_a":       # read r (+ p), S; write p, C K transformed rows
+        first = c8 * (2 * K + C + C * K)
+        rest = c8 * (3 * K + C + C * K)
+        return (first + (n_cg - 1) * rest) / n_cg
+    if kind == "pass_b":       # read + write the C K intermediate, read Psi (upper triangle, fp32)
+        return c8 * 2 * C * K + 4.0 * N * K * (K + 1) / 2
+    if kind == "pass_c":       # read C K intermediate, S, p; write w
+        return c8 * (C * K + C + 2 * K)
+    if kind == "cg_update":    # read x, r, p, w; write x, r
+        return c8 * 6 * K
+    if kind == "llr_admm":     # read alpha, u, z, r; write z, u, r
+        return c8 * 7 * K
+    if kind == "load_adjoint":
+        return None
+    raise KeyError(kind)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on the host cores, one slice per process
+# ---------------------------------------------------------------------------
+
+_CPU = {}
+
+
+def _oracle_job(i):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import t2s as O
+    d = _CPU
+    t0 = time.perf_counter()
+    O.admm(d["ksp"][i], d["sens"][i], d["phi"], d["masks"], d["lam"], d["rho"], d["block"], d["outer"], d["n_cg"],
+           d["seed"], g=int(d["g"][i]))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(cl, phi, cfg, n_procs, outer):
+    """Run the oracle on n_procs slices for `outer` outer iterations each, in parallel."""
+    sel = np.linspace(0, cl.nslices - 1, n_procs).round().astype(int)
+    _CPU.update(ksp=cl.ksp[sel], sens=cl.sens[sel], phi=phi, masks=cl.masks.astype(bool), lam=cfg["lam"],
+                rho=cfg["rho"], block=cfg["block"], outer=outer, n_cg=cfg["n_cg"], seed=cfg["seed"], g=sel)
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(n_procs) as pool:
+        per = pool.map(_oracle_job, range(n_procs))
+    wall = time.perf_counter() - t0
+    # full-schedule slices completed per second
+    frac = outer / cfg["n_outer"]
+    return dict(value=n_procs * frac / wall, unit="slices/s", cores=n_procs, kind="oracle",
+                sample=f"{n_procs} slices x {outer} of {cfg['n_outer']} ADMM outer iterations (5 CG), FP64 NumPy, "
+                       f"one process per slice, wall {wall:.1f} s, per-slice {np.mean(per):.1f} s",
+                s_per_volume=cl.nslices / (n_procs * frac / wall))
+
+
+# ---------------------------------------------------------------------------
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1, help="workload id (1: 320 x 256^2 volume)")
+    ap.add_argument("--mode", choices=["batched", "per_slice"], default="batched")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(16, cores))")
+    ap.add_argument("--cpu-outer", type=int, default=6, help="outer iterations of each oracle slice")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB device copy before timing (HBM counter calibration under rocprof)")
+    ap.add_argument("--traffic", type=str, default=None,
+                    help="JSON file with rocprof-measured HBM bytes per launch of the dominant kernel")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    from synth import make_config
+
+    t0 = time.perf_counter()
+    d = make_config(args.config)
+    cfg, phi = d["cfg"], d["phi"]
+    classes = d["classes"]
+    log(f"generated {cfg['name']} in {time.perf_counter() - t0:.1f} s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nprocs = args.cpu_procs or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(classes[0], phi, cfg, nprocs, args.cpu_outer)
+        log(f"cpu baseline: {cpu['value']:.4f} slices/s ({cpu['sample']})")
+
+    import torch
+
+    import paper_1809_04195_amd as T
+
+    assert torch.cuda.is_available(), "no GPU"
+    dev = torch.device("cuda:0")
+    plan = T.Plan(phi, [dict(ny=c.ny, nz=c.nz, ncoils=c.ncoils, nslices=c.nslices, masks=c.masks) for c in classes],
+                  lam=cfg["lam"], rho=cfg["rho"], block=cfg["block"], n_outer=cfg["n_outer"], n_cg=cfg["n_cg"],
+                  tol=cfg["tol"], seed=cfg["seed"])
+    dsens = [torch.from_numpy(np.ascontiguousarray(c.sens)).to(dev) for c in classes]
+    dksp = [torch.from_numpy(np.ascontiguousarray(c.ksp)).to(dev) for c in classes]
+    torch.cuda.synchronize()
+    log(f"workspace {plan.nbytes / 2**30:.2f} GiB, inputs resident in HBM")
+    if args.copy_probe:
+        a = torch.empty(2**28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read + 1 GiB write")
+    mode = T.T2S_BATCHED if args.mode == "batched" else T.T2S_PER_SLICE
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for ci in range(len(classes)):
+            T.t2s_load_slices(plan.handle, ci, 0, classes[ci].nslices, dsens[ci], dksp[ci], stream)
+        T.t2s_reconstruct(plan.handle, mode, stream)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    T.t2s_profile_enable(plan.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        log(f"timed step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s")
+    elapsed = time.perf_counter() - t0
+    prof = {name: T.t2s_profile_read(plan.handle, k) for k, name in enumerate(T.KERNEL_NAMES)}
+    T.t2s_profile_enable(plan.handle, False)
+
+    n_slices = sum(c.nslices for c in classes)
+    ms_per_step = elapsed * 1000.0 / args.steps
+    value = n_slices / (ms_per_step / 1000.0)
+
+    # dominant kernel: largest summed event time
+    kern = {}
+    for name, (n, ms) in prof.items():
+        if n == 0:
+            continue
+        per = []
+        for c in classes:
+            b = alg_bytes_per_slice(name, c.ny, c.nz, c.ncoils, phi.shape[1], cfg["n_cg"])
+            per.append(None if b is None else b * c.nslices)
+        nb = None if any(p is None for p in per) else sum(per) / len(classes)
+        kern[name] = dict(launches=n, total_ms=ms, avg_ms=ms / n,
+                          alg_bytes_per_launch=nb,
+                          achieved_gbs=(nb / (ms / n) / 1e6) if nb else None)
+    dom = max((k for k in kern if kern[k]["alg_bytes_per_launch"]), key=lambda k: kern[k]["total_ms"])
+    kd = kern[dom]
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        tr = json.load(open(args.traffic))
+        traffic = tr.get(dom)
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(kd["achieved_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
+                    avg_launch_ms=round(kd["avg_ms"], 4), alg_bytes_per_launch=int(kd["alg_bytes_per_launch"]))
+    # whole-solve algorithmic bandwidth (all kernel families with a byte model)
+    tot_bytes = sum(k["alg_bytes_per_launch"] * k["launches"] for k in kern.values() if k["alg_bytes_per_launch"])
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "s_per_volume": round(ms_per_step / 1000.0, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "slices": n_slices,
+                   "classes": [f"{c.nslices}x{c.ny}x{c.nz}c{c.ncoils}" for c in classes],
+                   "T": int(phi.shape[0]), "K": int(phi.shape[1]), "outer": cfg["n_outer"], "cg": cfg["n_cg"],
+                   "block": cfg["block"], "lambda": cfg["lam"], "rho": cfg["rho"], "mode": args.mode,
+                   "step": "load_slices(device inputs) + reconstruct"},
+        "roofline": roofline,
+        "solver_alg_gbs": round(tot_bytes / (elapsed * 1e9), 1),
+        "kernels": {k: dict(launches=v["launches"], avg_ms=round(v["avg_ms"], 4),
+                            achieved_gbs=None if v["achieved_gbs"] is None else round(v["achieved_gbs"], 1))
+                    for k, v in kern.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -180,6 +180,23 @@ int t2s_apply_llr(t2s_plan* plan, int cls, int first, int count, const void* in,
  * uncentred order, scaled by 1/(ny nz)) into host memory `out`. */
 int t2s_get_psi(const t2s_plan* plan, int cls, float* out);
 
+/* ---- Kernel timing (HIP events on the plan's stream, recorded around launches) ---- */
+
+#define T2S_KERNEL_PASS_A 0    /* S p + row FFT (first loop of Alg. 1)             */
+#define T2S_KERNEL_PASS_B 1    /* column FFT, Psi mix, column IFFT (second loop)    */
+#define T2S_KERNEL_PASS_C 2    /* row IFFT, coil combine, + rho p (third loop)      */
+#define T2S_KERNEL_CG 3        /* CG vector update                                  */
+#define T2S_KERNEL_LLR 4       /* LLR z-step fused with the ADMM updates            */
+#define T2S_KERNEL_LOAD 5      /* projection + adjoint of load_slices               */
+#define T2S_KERNEL_COUNT 6
+
+/* Enable (1) or disable (0) event timing of every launch; enabling clears the totals. */
+int t2s_profile_enable(t2s_plan* plan, int enable);
+
+/* Launch count and summed duration (ms) of kernel family `kernel` since the last
+ * enable.  Synchronises the events (call after the stream has finished). */
+int t2s_profile_read(t2s_plan* plan, int kernel, int* launches, double* total_ms);
+
 /* The library's own block-shift schedule: SplitMix64 (Steele, Lea & Flood 2014),
  * h = sm(sm(sm(seed) ^ g) ^ k), s_y = (h mod 2^32) mod b, s_z = (h >> 32) mod b, for
  * global slice index g (class-major order) and outer iteration k.  Host only. */

@@ -36,6 +36,13 @@ T2S_ALPHA = 0
 T2S_Z = 1
 T2S_U = 2
 T2S_ADJOINT = 3
+T2S_KERNEL_PASS_A = 0
+T2S_KERNEL_PASS_B = 1
+T2S_KERNEL_PASS_C = 2
+T2S_KERNEL_CG = 3
+T2S_KERNEL_LLR = 4
+T2S_KERNEL_LOAD = 5
+KERNEL_NAMES = ("pass_a", "pass_b", "pass_c", "cg_update", "llr_admm", "load_adjoint")
 
 
 class t2s_params(ctypes.Structure):
@@ -106,6 +113,9 @@ _SIGS = {
     "t2s_apply_llr": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                        ctypes.c_float, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p], ctypes.c_int),
     "t2s_get_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "t2s_profile_enable": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "t2s_profile_read": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
+                         ctypes.c_int),
     "t2s_block_shift": ([ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                          ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
 }
@@ -255,6 +265,16 @@ def t2s_apply_llr(plan, cls, first, count, inp, out, tau, shifts, stream=None):
     sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.int32).reshape(-1))
     return _check(lib().t2s_apply_llr(plan, cls, first, count, _ptr(inp), _ptr(out), tau,
                                       sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _stream(stream)))
+
+
+def t2s_profile_enable(plan, enable=True):
+    return _check(lib().t2s_profile_enable(plan, 1 if enable else 0))
+
+
+def t2s_profile_read(plan, kernel):
+    n, ms = ctypes.c_int(), ctypes.c_double()
+    _check(lib().t2s_profile_read(plan, kernel, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def t2s_get_psi(plan, cls, K, ny, nz):

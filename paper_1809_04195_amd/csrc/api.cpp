@@ -52,7 +52,16 @@ struct ClassPlan {
 
 }  // namespace
 
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;             // free events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> open[T2S_KERNEL_COUNT];
+    int launches[T2S_KERNEL_COUNT] = {};
+    double ms[T2S_KERNEL_COUNT] = {};
+};
+
 struct t2s_plan {
+    Profiler prof;
     t2s_params prm{};
     std::vector<float> phi;
     std::vector<ClassPlan> cls;
@@ -130,6 +139,59 @@ void fill_args(t2s_plan* plan, ClassPlan& c) {
     a.state = (int*)(b + c.o_state);
 }
 
+hipEvent_t prof_event(Profiler& p) {
+    if (!p.pool.empty()) {
+        hipEvent_t e = p.pool.back();
+        p.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Collect finished intervals of one kernel family into the totals.
+int prof_drain(Profiler& p, int kind) {
+    for (auto& pr : p.open[kind]) {
+        HIP_TRY(hipEventSynchronize(pr.second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        p.ms[kind] += ms;
+        p.launches[kind] += 1;
+        p.pool.push_back(pr.first);
+        p.pool.push_back(pr.second);
+    }
+    p.open[kind].clear();
+    return 0;
+}
+
+struct TimedLaunch {
+    Profiler* p;
+    int kind;
+    hipStream_t st;
+    hipEvent_t e0 = nullptr;
+    TimedLaunch(Profiler* p_, int k, hipStream_t s) : p(p_), kind(k), st(s) {
+        if (p && p->on) {
+            if (p->open[kind].size() > 4096) prof_drain(*p, kind);
+            e0 = prof_event(*p);
+            if (e0) hipEventRecord(e0, st);
+        }
+    }
+    ~TimedLaunch() {
+        if (e0) {
+            hipEvent_t e1 = prof_event(*p);
+            if (e1) {
+                hipEventRecord(e1, st);
+                p->open[kind].push_back({e0, e1});
+            }
+        }
+    }
+};
+
+thread_local Profiler* g_prof = nullptr;   // profiler of the plan being driven
+
+#define TIMED(kind) TimedLaunch timed_##__LINE__(g_prof, kind, st)
+
 PartialSrc rr_src(const ClassArgs& a, int buf) { return PartialSrc{a.rr + (size_t)buf * a.nrr, 2 * a.nrr, a.nrr}; }
 PartialSrc g0_src(const ClassArgs& a) { return PartialSrc{a.g0, a.nllr, a.nllr}; }
 
@@ -143,10 +205,19 @@ PartialSrc g0_src(const ClassArgs& a) { return PartialSrc{a.g0, a.nllr, a.nllr};
 // w = (A^H A + rho_add) applied to src (slices [s0, s0+count), src indexed from src_s0)
 int run_normal(const ClassArgs& a, int s0, int count, const float2* src, int src_s0, float rho_add, float2* out,
                int out_s0, hipStream_t st) {
-    HIP_CHECK_LAUNCH(t2s::launch_passA(a, s0, count, src, src_s0, 1, PartialSrc{nullptr, 0, 0},
-                                       PartialSrc{nullptr, 0, 0}, st));
-    HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, st));
-    HIP_CHECK_LAUNCH(t2s::launch_passC(a, s0, count, 0, rho_add, out, out_s0, st));
+    {
+        TIMED(T2S_KERNEL_PASS_A);
+        HIP_CHECK_LAUNCH(t2s::launch_passA(a, s0, count, src, src_s0, 1, PartialSrc{nullptr, 0, 0},
+                                           PartialSrc{nullptr, 0, 0}, st));
+    }
+    {
+        TIMED(T2S_KERNEL_PASS_B);
+        HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, st));
+    }
+    {
+        TIMED(T2S_KERNEL_PASS_C);
+        HIP_CHECK_LAUNCH(t2s::launch_passC(a, s0, count, 0, rho_add, out, out_s0, st));
+    }
     return 0;
 }
 
@@ -157,13 +228,28 @@ int run_outer(const t2s_plan* plan, const ClassArgs& a, int s0, int count, int k
         const PartialSrc none{nullptr, 0, 0};
         const PartialSrc gcA = (i == 0) ? none : rr_src(a, i % 2);
         const PartialSrc gpA = (i == 0) ? none : (i == 1 ? g0_src(a) : rr_src(a, (i - 1) % 2));
-        HIP_CHECK_LAUNCH(t2s::launch_passA(a, s0, count, a.r, 0, i == 0 ? 1 : 0, gcA, gpA, st));
-        HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, st));
-        HIP_CHECK_LAUNCH(t2s::launch_passC(a, s0, count, 0, a.rho, a.w, 0, st));
+        {
+            TIMED(T2S_KERNEL_PASS_A);
+            HIP_CHECK_LAUNCH(t2s::launch_passA(a, s0, count, a.r, 0, i == 0 ? 1 : 0, gcA, gpA, st));
+        }
+        {
+            TIMED(T2S_KERNEL_PASS_B);
+            HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, st));
+        }
+        {
+            TIMED(T2S_KERNEL_PASS_C);
+            HIP_CHECK_LAUNCH(t2s::launch_passC(a, s0, count, 0, a.rho, a.w, 0, st));
+        }
         const PartialSrc gcU = (i == 0) ? g0_src(a) : rr_src(a, i % 2);
-        HIP_CHECK_LAUNCH(t2s::launch_cg_update(a, s0, count, gcU, (i + 1) % 2, st));
+        {
+            TIMED(T2S_KERNEL_CG);
+            HIP_CHECK_LAUNCH(t2s::launch_cg_update(a, s0, count, gcU, (i + 1) % 2, st));
+        }
     }
-    HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrAdmm, k, nullptr, nullptr, a.tau, 0, 0, st));
+    {
+        TIMED(T2S_KERNEL_LLR);
+        HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrAdmm, k, nullptr, nullptr, a.tau, 0, 0, st));
+    }
     HIP_CHECK_LAUNCH(t2s::launch_llr_finalize(a, s0, count, k, st));
     return 0;
 }
@@ -330,7 +416,37 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
 }
 
 int t2s_plan_destroy(t2s_plan* plan) {
+    if (plan) {
+        for (int k = 0; k < T2S_KERNEL_COUNT; ++k)
+            for (auto& pr : plan->prof.open[k]) {
+                hipEventDestroy(pr.first);
+                hipEventDestroy(pr.second);
+            }
+        for (hipEvent_t e : plan->prof.pool) hipEventDestroy(e);
+        if (g_prof == &plan->prof) g_prof = nullptr;
+    }
     delete plan;
+    return 0;
+}
+
+int t2s_profile_enable(t2s_plan* plan, int enable) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    Profiler& p = plan->prof;
+    for (int k = 0; k < T2S_KERNEL_COUNT; ++k) {
+        if (int e = prof_drain(p, k)) return e;
+        p.launches[k] = 0;
+        p.ms[k] = 0.0;
+    }
+    p.on = enable != 0;
+    return 0;
+}
+
+int t2s_profile_read(t2s_plan* plan, int kernel, int* launches, double* total_ms) {
+    if (!plan || !launches || !total_ms) return fail(T2S_EINVAL, "NULL argument");
+    if (kernel < 0 || kernel >= T2S_KERNEL_COUNT) return fail(T2S_EINVAL, "bad kernel id");
+    if (int e = prof_drain(plan->prof, kernel)) return e;
+    *launches = plan->prof.launches[kernel];
+    *total_ms = plan->prof.ms[kernel];
     return 0;
 }
 
@@ -398,10 +514,14 @@ int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* s
     HIP_TRY(hipMemcpyAsync(a.sens + (size_t)first * c.C * N, sens, ns * 4, kind, st));
     if (nk) HIP_TRY(hipMemcpyAsync(a.ksp + (size_t)first * c.C * c.P, ksp, nk * 4, kind, st));
     HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, st));
-    HIP_CHECK_LAUNCH(t2s::launch_project(a, first, count, st));
-    HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, st));
-    HIP_CHECK_LAUNCH(t2s::launch_passC(a, first, count, 1, 0.0f, a.b0, 0, st));
-    HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, nullptr, 0, st));
+    {
+        g_prof = &plan->prof;
+        TIMED(T2S_KERNEL_LOAD);
+        HIP_CHECK_LAUNCH(t2s::launch_project(a, first, count, st));
+        HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, st));
+        HIP_CHECK_LAUNCH(t2s::launch_passC(a, first, count, 1, 0.0f, a.b0, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, nullptr, 0, st));
+    }
     if (mem == T2S_HOST) HIP_TRY(hipStreamSynchronize(st));
     for (int i = 0; i < count; ++i) c.loaded[first + i] = 1;
     plan->last_stream = st;
@@ -423,6 +543,7 @@ int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* a
             if (!finite_f(f[i])) return fail(T2S_ENONFINITE, "alpha0 contains NaN/Inf");
     }
     hipStream_t st = (hipStream_t)stream;
+    g_prof = &plan->prof;
     const ClassArgs& a = c.args;
     float2* xs = a.x + (size_t)first * K * c.ny * c.nz;
     HIP_TRY(hipMemcpyAsync(xs, alpha0, n * 4, mem == T2S_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
@@ -443,6 +564,7 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
             if (!c.loaded[s]) return fail(T2S_ESTATE, "not every slice is loaded");
     hipStream_t st = (hipStream_t)stream;
     plan->last_stream = st;
+    g_prof = &plan->prof;
     const t2s_params& prm = plan->prm;
     const bool tolmode = prm.tol > 0;
     for (ClassPlan& c : plan->cls) {
@@ -576,6 +698,7 @@ int t2s_apply_normal(t2s_plan* plan, int cls, int first, int count, const void* 
     for (int i = 0; i < count; ++i)
         if (!c.loaded[first + i]) return fail(T2S_ESTATE, "slice not loaded");
     hipStream_t st = (hipStream_t)stream;
+    g_prof = &plan->prof;
     HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, first, count, 1, -1, st));
     return run_normal(c.args, first, count, (const float2*)in, first, rho_add, (float2*)out, first, st);
 }

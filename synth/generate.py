@@ -34,6 +34,8 @@ of a volume is generated bit-identically to the same slices of the full volume.
 from __future__ import annotations
 
 import dataclasses
+import mmap
+import multiprocessing as mp
 import os
 
 import numpy as np
@@ -262,7 +264,7 @@ def vd_poisson_masks(seed, T, ny, nz, frac, center_frac=None):
 
 def _fft2c(x):
     ax = (-2, -1)
-    workers = min(16, os.cpu_count() or 1)
+    workers = 1 if mp.current_process().name != "MainProcess" else min(16, os.cpu_count() or 1)
     return sfft.fftshift(sfft.fft2(sfft.ifftshift(x, axes=ax), axes=ax, norm="ortho", workers=workers), axes=ax)
 
 
@@ -317,7 +319,31 @@ class SliceSet:
         return self.sens.shape[0]
 
 
-def _class_slices(cfg, cl, slices):
+def _shared_empty(shape, dtype):
+    """Zeroed array in an anonymous shared mapping (visible to forked workers)."""
+    nbytes = int(np.prod(shape)) * np.dtype(dtype).itemsize
+    buf = mmap.mmap(-1, max(nbytes, 1))
+    return np.frombuffer(buf, dtype=dtype, count=int(np.prod(shape))).reshape(shape)
+
+
+_JOB = {}
+
+
+def _slice_job(i):
+    j = _JOB
+    ix = int(j["slices"][i])
+    if j["dims"] == 3:
+        lab = labels_3d_slice(j["ells"], j["nx"], ix, j["ny"], j["nz"])
+        s2 = coils_3d_slice(j["C"], j["nx"], ix, j["ny"], j["nz"])
+    else:
+        lab, s2 = j["lab"], j["s2"]
+    rng = np.random.default_rng([j["seed"], 2, ix])
+    j["sens"][i] = s2
+    j["ksp"][i] = acquire(lab, j["pd"], j["t2"], s2, j["masks"], j["snr"], rng, locs=j["locs"])
+    return i
+
+
+def _class_slices(cfg, cl, slices, workers=None):
     seed = cl.get("seed", cfg["seed"])
     T = cfg["T"]
     ny, nz, C = cl["ny"], cl["nz"], cl["ncoils"]
@@ -331,28 +357,40 @@ def _class_slices(cfg, cl, slices):
         else:                                   # evenly spaced inside the central half
             slices = np.round(np.linspace(nx // 4, 3 * nx // 4 - 1, cl["nslices"])).astype(int)
     slices = np.asarray(slices, dtype=int)
-    sens = np.empty((len(slices), C, ny, nz), dtype=np.complex64)
-    ksp = np.empty((len(slices), C, ptot), dtype=np.complex64)
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    workers = max(1, min(workers, len(slices) // 4))
+    alloc = _shared_empty if workers > 1 else np.zeros
+    sens = alloc((len(slices), C, ny, nz), np.complex64)
+    ksp = alloc((len(slices), C, ptot), np.complex64)
     vrng = np.random.default_rng([seed, 1])
+    job = dict(dims=cfg["dims"], ny=ny, nz=nz, nx=nx, C=C, seed=seed, masks=masks, locs=locs, snr=cfg["snr"],
+               sens=sens, ksp=ksp, slices=slices)
     if cfg["dims"] == 2:
         ells = draw_ellipses(vrng)
-        lab = labels_2d(ells, ny, nz)
-        s2 = coils_2d(C, ny, nz)
+        job["lab"] = labels_2d(ells, ny, nz)
+        job["s2"] = coils_2d(C, ny, nz)
     else:
         ells = draw_ellipsoids(vrng)
-    pd = np.array([e["pd"] for e in ells])
-    t2 = np.array([e["t2"] for e in ells])
-    for i, ix in enumerate(slices):
-        if cfg["dims"] == 3:
-            lab = labels_3d_slice(ells, nx, ix, ny, nz)
-            s2 = coils_3d_slice(C, nx, ix, ny, nz)
-        rng = np.random.default_rng([seed, 2, int(ix)])
-        sens[i] = s2
-        ksp[i] = acquire(lab, pd, t2, s2, masks, cfg["snr"], rng, locs=locs)
+    job["ells"] = ells
+    job["pd"] = np.array([e["pd"] for e in ells])
+    job["t2"] = np.array([e["t2"] for e in ells])
+    _JOB.clear()
+    _JOB.update(job)
+    if workers > 1:
+        # forked workers write their slices straight into the shared arrays; every slice
+        # depends only on (seed, slice index), so the result does not depend on `workers`
+        with mp.get_context("fork").Pool(workers) as pool:
+            for _ in pool.imap_unordered(_slice_job, range(len(slices)), chunksize=2):
+                pass
+    else:
+        for i in range(len(slices)):
+            _slice_job(i)
+    _JOB.clear()
     return SliceSet(ny, nz, C, masks, sens, ksp, slices)
 
 
-def make_config(cfg_id: int, slices=None, max_slices=None):
+def make_config(cfg_id: int, slices=None, max_slices=None, workers=None):
     """Generate workload ``cfg_id``.  ``slices`` selects readout positions (single
     class workloads); ``max_slices`` keeps the first n of each class."""
     cfg = dict(CONFIGS[cfg_id])
@@ -366,7 +404,7 @@ def make_config(cfg_id: int, slices=None, max_slices=None):
                 sel = np.arange(nx)[:max_slices]
             else:
                 sel = np.round(np.linspace(nx // 4, 3 * nx // 4 - 1, cl["nslices"])).astype(int)[:max_slices]
-        classes.append(_class_slices(cfg, cl, sel))
+        classes.append(_class_slices(cfg, cl, sel, workers))
     return dict(cfg=cfg, phi=phi, classes=classes)
 
 
