@@ -318,6 +318,47 @@ T2S_INL float2* fft_emulate(float2* a, float2* b, int ntr, int ld, const float2*
     return fft_emulate_unpack<L, INV>(typename FftPlan<L>::type{}, a, b, ntr, ld, tw);
 }
 
+// ---------------------------------------------------------------------------
+// Two-step ("four-step") register plans: L = R1 * R2.
+//   forward step 1: thread n2 < R2 holds x[R2 n1 + n2] (n1 < R1), DFT_R1, then
+//                   multiplies output k1 by W_L^(n2 k1) and writes it to an LDS
+//                   exchange slot (k1, n2);
+//   forward step 3: thread k1 < R1 reads slots (k1, n2 < R2), DFT_R2, and holds
+//                   X[k1 + R1 k2] (k2 < R2).
+//   inverse step 1: thread k1 < R1 holds X[k1 + R1 k2], inverse DFT_R2, multiplies
+//                   output m1 by W_L^-(k1 m1), writes slot (m1, k1);
+//   inverse step 3: thread m1 < R2 reads slots (m1, k1 < R1), inverse DFT_R1, and
+//                   holds x[m1 + R2 m2] (m2 < R1).
+// So each transform crosses LDS once, and a forward transform followed by an
+// inverse one needs no exchange in between (the frequency-side layouts match).
+// ---------------------------------------------------------------------------
+template <int L>
+struct RegPlan;
+template <> struct RegPlan<16> { static constexpr int R1 = 4, R2 = 4; };
+template <> struct RegPlan<32> { static constexpr int R1 = 4, R2 = 8; };
+template <> struct RegPlan<48> { static constexpr int R1 = 6, R2 = 8; };
+template <> struct RegPlan<64> { static constexpr int R1 = 8, R2 = 8; };
+template <> struct RegPlan<96> { static constexpr int R1 = 12, R2 = 8; };
+template <> struct RegPlan<128> { static constexpr int R1 = 8, R2 = 16; };
+template <> struct RegPlan<160> { static constexpr int R1 = 10, R2 = 16; };
+template <> struct RegPlan<192> { static constexpr int R1 = 12, R2 = 16; };
+template <> struct RegPlan<256> { static constexpr int R1 = 16, R2 = 16; };
+template <> struct RegPlan<320> { static constexpr int R1 = 20, R2 = 16; };
+template <> struct RegPlan<384> { static constexpr int R1 = 24, R2 = 16; };
+template <> struct RegPlan<512> { static constexpr int R1 = 32, R2 = 16; };
+
+template <int L>
+struct RegGeom {
+    static constexpr int R1 = RegPlan<L>::R1;
+    static constexpr int R2 = RegPlan<L>::R2;
+    static_assert(R1 * R2 == L, "plan does not factor L");
+    static constexpr int P = R1 > R2 ? R1 : R2;              // threads per transform
+    static constexpr int S1 = R2 + 1;                         // forward slot stride (k1 rows)
+    static constexpr int S2 = R1 + 1;                         // inverse slot stride (m1 rows)
+    static constexpr int TB0 = R1 * R2 + P;                   // >= R1 * S1 and >= R2 * S2
+    static constexpr int TB = TB0 + ((17 - TB0 % 16) % 16);   // per-transform LDS words, == 1 mod 16
+};
+
 #if defined(__HIPCC__)
 // Device LDS FFT of ntr transforms, all threads of the workgroup taking part.
 // Input in `a` (padded layout); returns the buffer (a or b) that holds the result.

@@ -64,19 +64,31 @@ __host__ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
     return z ^ (z >> 31);
 }
 
+// x * W_L^(+-e) with the twiddle read from the LDS table (0 <= e < L)
+template <bool INV>
+__device__ __forceinline__ float2 tw_mul(float2 x, const float2* tw, int e) {
+    if (e == 0) return x;
+    float2 w = tw[e];
+    if (INV) w.y = -w.y;
+    return cmul(x, w);
+}
+
+template <int L>
+constexpr int rows_threads() { return kRowTile * RegGeom<L>::P; }
+
 // ---------------------------------------------------------------------------
-// pass A
+// pass A: per (row tile, k): p = r + beta p, then per coil S_c p_k and the row FFT
+// (register two-step plan), stored transposed.  Two thread mappings meet at the
+// LDS exchange: row-major lanes for the coalesced row loads, row-fastest lanes for
+// the coalesced transposed stores.
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(kThreads) void k_passA(ClassArgs a, int s0, const float2* __restrict__ src, int src_s0,
-                                                     int first, PartialSrc gc, PartialSrc gp) {
-    constexpr int RT = kRowTile;
-    constexpr int LD = lds_ld(L);
-    constexpr int EPT = (RT * L + kThreads - 1) / kThreads;
-    extern __shared__ float2 lds[];
-    float2* tw = lds;
-    float2* buf0 = lds + L;
-    float2* buf1 = buf0 + RT * LD;
+__global__ __launch_bounds__(rows_threads<L>()) void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
+                                                              int src_s0, int first, PartialSrc gc, PartialSrc gp) {
+    using G = RegGeom<L>;
+    constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
+    __shared__ float2 tw[L];
+    __shared__ float2 xb[RT * TB];
 
     const int s = s0 + blockIdx.z;
     if (!slice_active(a, s)) return;
@@ -85,136 +97,220 @@ __global__ __launch_bounds__(kThreads) void k_passA(ClassArgs a, int s0, const f
     const int ny = a.ny;
     const size_t N = (size_t)ny * L;
     const int tid = threadIdx.x;
+    for (int i = tid; i < L; i += NT) tw[i] = a.twz[i];
 
-    for (int i = tid; i < L; i += kThreads) tw[i] = a.twz[i];
+    const int r1 = tid / P, t1 = tid - r1 * P;   // mapping 1 (t fastest)
+    const bool on1 = t1 < R2;
+    const int r3 = tid % RT, t3 = tid / RT;      // mapping 3 (row fastest)
+    const bool on3 = t3 < R1;
 
     float beta = 0.0f;
     if (!first) {
         const double g1 = partial_sum(gc, s), g0 = partial_sum(gp, s);
         beta = g0 > 0.0 ? (float)(g1 / g0) : 0.0f;
     }
-    const size_t vbase = ((size_t)s * a.K + k) * N + (size_t)y0 * L;
-    const float2* rs = src + ((size_t)(s - src_s0) * a.K + k) * N + (size_t)y0 * L;
-    float2* ps = a.p + vbase;
-    float2 pv[EPT];
+    const size_t rowoff = (size_t)(y0 + r1) * L;
+    const float2* rs = src + ((size_t)(s - src_s0) * a.K + k) * N + rowoff;
+    float2* ps = a.p + ((size_t)s * a.K + k) * N + rowoff;
+    float2 pv[R1];
+    if (on1) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * kThreads;
-        if (e < RT * L) {
-            float2 v = rs[e];
+        for (int n1 = 0; n1 < R1; ++n1) {
+            const int pos = R2 * n1 + t1;
+            float2 v = rs[pos];
             if (!first) {
-                const float2 po = ps[e];
+                const float2 po = ps[pos];
                 v = make_float2(v.x + beta * po.x, v.y + beta * po.y);
             }
-            ps[e] = v;
-            pv[i] = v;
+            ps[pos] = v;
+            pv[n1] = v;
         }
     }
+    __syncthreads();
+    float2* xr1 = xb + r1 * TB;
+    const float2* xr3 = xb + r3 * TB;
     for (int c = 0; c < a.C; ++c) {
-        const float2* S = a.sens + ((size_t)s * a.C + c) * N + (size_t)y0 * L;
+        if (on1) {
+            const float2* S = a.sens + ((size_t)s * a.C + c) * N + rowoff;
+            float2 v[R1];
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * kThreads;
-            if (e < RT * L) {
-                const int row = e / L, zc = e - row * L;
-                buf0[row * LD + ph(zc)] = cmul(S[e], pv[i]);
-            }
+            for (int n1 = 0; n1 < R1; ++n1) v[n1] = cmul(S[R2 * n1 + t1], pv[n1]);
+            dft_dir<R1, false>(v);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) xr1[k1 * (R2 + 1) + t1] = tw_mul<false>(v[k1], tw, t1 * k1);
         }
         __syncthreads();
-        const float2* res = fft_lds<L, false>(buf0, buf1, RT, LD, tw);
-        float2* out = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + y0;
-        for (int e = tid; e < RT * L; e += kThreads) {
-            const int row = e % RT, zc = e / RT;
-            out[(size_t)zc * ny + row] = res[row * LD + ph(zc)];
+        if (on3) {
+            float2 b[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) b[n2] = xr3[t3 * (R2 + 1) + n2];
+            dft_dir<R2, false>(b);
+            float2* out = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + y0 + r3;
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) out[(size_t)(t3 + R1 * k2) * ny] = b[k2];
         }
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// pass B
+// pass B: per (coil, column tile): forward column FFT of all K images, the K x K
+// Psi mix at every frequency (all K spectra of a column are held by the same
+// thread), inverse column FFT; in place.  MODE 1 (adjoint): inverse FFT only of
+// natural-order spectra.
 // ---------------------------------------------------------------------------
-template <int L, int MODE>
-__global__ __launch_bounds__(kThreads) void k_passB(ClassArgs a, int s0, int W) {
-    constexpr int LD = lds_ld(L);
-    extern __shared__ float2 lds[];
-    float2* tw = lds;
-    const int K = a.K;
-    float2* buf0 = lds + L;
-    float2* buf1 = buf0 + K * W * LD;
+template <int L>
+constexpr int colB() { return 256 / RegGeom<L>::P; }
+
+template <int L, int K>
+__global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a, int s0) {
+    using G = RegGeom<L>;
+    constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, W = colB<L>(), NT = W * P;
+    __shared__ float2 tw[L];
+    __shared__ float2 xb[W * TB];
 
     const int s = s0 + blockIdx.z;
     if (!slice_active(a, s)) return;
     const int c = blockIdx.y;
-    const int z0 = blockIdx.x * W;
-    const int nz = a.nz;
-    const size_t N = (size_t)L * nz;
     const int tid = threadIdx.x;
-    for (int i = tid; i < L; i += kThreads) tw[i] = a.twy[i];
-
-    float2* base = a.tmp + ((size_t)s * a.C + c) * K * N + (size_t)z0 * L;
-    const int ntr = K * W;
-    for (int e = tid; e < ntr * L; e += kThreads) {
-        const int tr = e / L, i = e - tr * L;
-        const int k = tr / W, w = tr - k * W;
-        buf0[tr * LD + ph(i)] = base[(size_t)k * N + (size_t)w * L + i];
-    }
+    const int w = tid / P, t = tid - w * P;
+    const int nz = a.nz;
+    const int z = blockIdx.x * W + w;
+    const bool colok = z < nz;
+    const size_t N = (size_t)L * nz;
+    for (int i = tid; i < L; i += NT) tw[i] = a.twy[i];
     __syncthreads();
-    float2* res;
-    if constexpr (MODE == 0) {
-        float2* f = fft_lds<L, false>(buf0, buf1, ntr, LD, tw);
-        for (int e = tid; e < W * L; e += kThreads) {
-            const int w = e / L, i = e - w * L;
-            const size_t pidx = (size_t)(z0 + w) * L + i;
-            float2 v[kMaxK];
+    float2* col = a.tmp + ((size_t)s * a.C + c) * (size_t)K * N + (size_t)(colok ? z : 0) * L;
+    float2* xw = xb + w * TB;
+
+    float2 F[K][R2];
 #pragma unroll
-            for (int kk = 0; kk < kMaxK; ++kk)
-                if (kk < K) v[kk] = f[(kk * W + w) * LD + ph(i)];
+    for (int k = 0; k < K; ++k) {
+        if (t < R2) {
+            float2 v[R1];
 #pragma unroll
-            for (int kk = 0; kk < kMaxK; ++kk) {
-                if (kk < K) {
-                    float2 acc = make_float2(0.f, 0.f);
+            for (int n1 = 0; n1 < R1; ++n1) v[n1] = colok ? col[(size_t)k * N + R2 * n1 + t] : make_float2(0.f, 0.f);
+            dft_dir<R1, false>(v);
 #pragma unroll
-                    for (int l = 0; l < kMaxK; ++l) {
-                        if (l < K) {
-                            const int lo = kk < l ? kk : l, hi = kk < l ? l : kk;
-                            const int tri = lo * K - (lo * (lo - 1)) / 2 + (hi - lo);
-                            const float q = a.psi[(size_t)tri * N + pidx];
-                            acc.x += q * v[l].x;
-                            acc.y += q * v[l].y;
-                        }
-                    }
-                    f[(kk * W + w) * LD + ph(i)] = acc;
+            for (int k1 = 0; k1 < R1; ++k1) xw[k1 * (R2 + 1) + t] = tw_mul<false>(v[k1], tw, t * k1);
+        }
+        __syncthreads();
+        if (t < R1) {
+            float2 b[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) b[n2] = xw[t * (R2 + 1) + n2];
+            dft_dir<R2, false>(b);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) F[k][k2] = b[k2];
+        }
+        __syncthreads();
+    }
+    if (t < R1 && colok) {
+        const float* psi = a.psi + (size_t)z * L + t;
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+            const size_t off = (size_t)R1 * k2;
+            float2 v[K];
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) v[kk] = F[kk][k2];
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int l = 0; l < K; ++l) {
+                    const int lo = kk < l ? kk : l, hi = kk < l ? l : kk;
+                    const int tri = lo * K - (lo * (lo - 1)) / 2 + (hi - lo);
+                    const float q = psi[(size_t)tri * N + off];
+                    acc.x += q * v[l].x;
+                    acc.y += q * v[l].y;
                 }
+                F[kk][k2] = acc;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (t < R1) {
+            float2 b[R2];
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) b[k2] = F[k][k2];
+            dft_dir<R2, true>(b);
+#pragma unroll
+            for (int m1 = 0; m1 < R2; ++m1) xw[m1 * (R1 + 1) + t] = tw_mul<true>(b[m1], tw, t * m1);
+        }
+        __syncthreads();
+        if (t < R2) {
+            float2 v[R1];
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) v[k1] = xw[t * (R1 + 1) + k1];
+            dft_dir<R1, true>(v);
+            if (colok) {
+#pragma unroll
+                for (int m2 = 0; m2 < R1; ++m2) col[(size_t)k * N + t + R2 * m2] = v[m2];
             }
         }
         __syncthreads();
-        float2* other = (f == buf0) ? buf1 : buf0;
-        res = fft_lds<L, true>(f, other, ntr, LD, tw);
-    } else {
-        res = fft_lds<L, true>(buf0, buf1, ntr, LD, tw);
     }
-    for (int e = tid; e < ntr * L; e += kThreads) {
-        const int tr = e / L, i = e - tr * L;
-        const int k = tr / W, w = tr - k * W;
-        base[(size_t)k * N + (size_t)w * L + i] = res[tr * LD + ph(i)];
+}
+
+template <int L>
+__global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassArgs a, int s0) {
+    using G = RegGeom<L>;
+    constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, W = colB<L>(), NT = W * P;
+    __shared__ float2 tw[L];
+    __shared__ float2 xb[W * TB];
+
+    const int s = s0 + blockIdx.z;
+    if (!slice_active(a, s)) return;
+    const int c = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int w = tid / P, t = tid - w * P;
+    const int nz = a.nz;
+    const int z = blockIdx.x * W + w;
+    const bool colok = z < nz;
+    const size_t N = (size_t)L * nz;
+    for (int i = tid; i < L; i += NT) tw[i] = a.twy[i];
+    __syncthreads();
+    float2* col = a.tmp + ((size_t)s * a.C + c) * (size_t)a.K * N + (size_t)(colok ? z : 0) * L;
+    float2* xw = xb + w * TB;
+    for (int k = 0; k < a.K; ++k) {
+        if (t < R1) {
+            float2 b[R2];
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2)
+                b[k2] = colok ? col[(size_t)k * N + t + R1 * k2] : make_float2(0.f, 0.f);
+            dft_dir<R2, true>(b);
+#pragma unroll
+            for (int m1 = 0; m1 < R2; ++m1) xw[m1 * (R1 + 1) + t] = tw_mul<true>(b[m1], tw, t * m1);
+        }
+        __syncthreads();
+        if (t < R2) {
+            float2 v[R1];
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) v[k1] = xw[t * (R1 + 1) + k1];
+            dft_dir<R1, true>(v);
+            if (colok) {
+#pragma unroll
+                for (int m2 = 0; m2 < R1; ++m2) col[(size_t)k * N + t + R2 * m2] = v[m2];
+            }
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// pass C
+// pass C: per (row tile, k): for every coil, read the transposed spectra (row-
+// fastest lanes), inverse row FFT, conj(S_c) (.) accumulated in registers; then
+// w = acc + rho p and the partial <p, w> (MODE 0), or b0 = acc (MODE 1).
 // ---------------------------------------------------------------------------
 template <int L, int MODE>
-__global__ __launch_bounds__(kThreads) void k_passC(ClassArgs a, int s0, float rho_add, float2* __restrict__ outp,
-                                                     int out_s0) {
-    constexpr int RT = kRowTile;
-    constexpr int LD = lds_ld(L);
-    constexpr int EPT = (RT * L + kThreads - 1) / kThreads;
-    extern __shared__ float2 lds[];
-    float2* tw = lds;
-    float2* buf0 = lds + L;
-    float2* buf1 = buf0 + RT * LD;
-    __shared__ double red[kThreads / 64];
+__global__ __launch_bounds__(rows_threads<L>()) void k_passC(ClassArgs a, int s0, float rho_add,
+                                                              float2* __restrict__ outp, int out_s0) {
+    using G = RegGeom<L>;
+    constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
+    __shared__ float2 tw[L];
+    __shared__ float2 xb[RT * TB];
+    __shared__ double red[16];
 
     const int s = s0 + blockIdx.z;
     if (!slice_active(a, s)) return;
@@ -223,54 +319,62 @@ __global__ __launch_bounds__(kThreads) void k_passC(ClassArgs a, int s0, float r
     const int ny = a.ny;
     const size_t N = (size_t)ny * L;
     const int tid = threadIdx.x;
-    for (int i = tid; i < L; i += kThreads) tw[i] = a.twz[i];
+    for (int i = tid; i < L; i += NT) tw[i] = a.twz[i];
+    __syncthreads();
 
-    float2 acc[EPT];
+    const int r1 = tid / P, t1 = tid - r1 * P;
+    const bool on1 = t1 < R2;
+    const int r3 = tid % RT, t3 = tid / RT;
+    const bool on3 = t3 < R1;
+    const size_t rowoff = (size_t)(y0 + r1) * L;
+    float2* xr1 = xb + r1 * TB;
+    float2* xr3 = xb + r3 * TB;
+
+    float2 acc[R1];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) acc[i] = make_float2(0.f, 0.f);
-
+    for (int i = 0; i < R1; ++i) acc[i] = make_float2(0.f, 0.f);
     for (int c = 0; c < a.C; ++c) {
-        const float2* in = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + y0;
-        for (int e = tid; e < RT * L; e += kThreads) {
-            const int row = e % RT, zc = e / RT;
-            buf0[row * LD + ph(zc)] = in[(size_t)zc * ny + row];
+        if (on3) {
+            const float2* in = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + y0 + r3;
+            float2 b[R2];
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) b[k2] = in[(size_t)(t3 + R1 * k2) * ny];
+            dft_dir<R2, true>(b);
+#pragma unroll
+            for (int m1 = 0; m1 < R2; ++m1) xr3[m1 * (R1 + 1) + t3] = tw_mul<true>(b[m1], tw, t3 * m1);
         }
         __syncthreads();
-        const float2* res = fft_lds<L, true>(buf0, buf1, RT, LD, tw);
-        const float2* S = a.sens + ((size_t)s * a.C + c) * N + (size_t)y0 * L;
+        if (on1) {
+            float2 v[R1];
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * kThreads;
-            if (e < RT * L) {
-                const int row = e / L, zc = e - row * L;
-                const float2 v = cmulc(res[row * LD + ph(zc)], S[e]);
-                acc[i] = cadd(acc[i], v);
-            }
+            for (int k1 = 0; k1 < R1; ++k1) v[k1] = xr1[t1 * (R1 + 1) + k1];
+            dft_dir<R1, true>(v);
+            const float2* S = a.sens + ((size_t)s * a.C + c) * N + rowoff;
+#pragma unroll
+            for (int m2 = 0; m2 < R1; ++m2) acc[m2] = cadd(acc[m2], cmulc(v[m2], S[t1 + R2 * m2]));
         }
         __syncthreads();
     }
-    const size_t vbase = ((size_t)s * a.K + k) * N + (size_t)y0 * L;
-    float2* out = outp + ((size_t)(s - out_s0) * a.K + k) * N + (size_t)y0 * L;
+    float2* out = outp + ((size_t)(s - out_s0) * a.K + k) * N + rowoff;
     if constexpr (MODE == 0) {
-        const float2* pp = a.p + vbase;
+        const float2* pp = a.p + ((size_t)s * a.K + k) * N + rowoff;
         double dot = 0.0;
+        if (on1) {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * kThreads;
-            if (e < RT * L) {
-                const float2 pv = pp[e];
-                const float2 w = make_float2(acc[i].x + rho_add * pv.x, acc[i].y + rho_add * pv.y);
-                out[e] = w;
+            for (int m2 = 0; m2 < R1; ++m2) {
+                const int pos = t1 + R2 * m2;
+                const float2 pv = pp[pos];
+                const float2 w = make_float2(acc[m2].x + rho_add * pv.x, acc[m2].y + rho_add * pv.y);
+                out[pos] = w;
                 dot += (double)pv.x * (double)w.x + (double)pv.y * (double)w.y;
             }
         }
         const double tot = block_sum(dot, red);
         if (tid == 0) a.pw[(size_t)s * a.npw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
     } else {
+        if (on1) {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * kThreads;
-            if (e < RT * L) out[e] = acc[i];
+            for (int m2 = 0; m2 < R1; ++m2) out[t1 + R2 * m2] = acc[m2];
         }
     }
 }
@@ -604,72 +708,99 @@ __global__ void k_llr_finalize(ClassArgs a, int s0, int k) {
 
 bool fft_supported(int L) { return fft_length_supported(L); }
 
-static size_t lds_rows(int L) { return (size_t)(L + 2 * kRowTile * lds_ld(L)) * sizeof(float2); }
-
-size_t lds_bytes_passA(int nz) { return lds_rows(nz); }
-
-int passB_columns(int ny, int K) {
-    // columns per workgroup: as many as fit 64 KiB of ping-pong LDS, at most 4
-    int W = 4;
-    while (W > 1 && (size_t)(ny + 2 * K * W * lds_ld(ny)) * sizeof(float2) > 65536) W >>= 1;
-    return W;
-}
-
-size_t lds_bytes_passB(int ny, int K) {
-    const int W = passB_columns(ny, K);
-    return (size_t)(ny + 2 * K * W * lds_ld(ny)) * sizeof(float2);
-}
+template <int L>
+static size_t rows_lds() { return (L + kRowTile * RegGeom<L>::TB) * sizeof(float2) + 16 * sizeof(double); }
+template <int L>
+static size_t cols_lds() { return (L + colB<L>() * RegGeom<L>::TB) * sizeof(float2); }
 
 #define T2S_FOR_LENGTHS(X) X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+
+size_t lds_bytes_passA(int nz) {
+    switch (nz) {
+#define X(L) case L: return rows_lds<L>();
+        T2S_FOR_LENGTHS(X)
+#undef X
+    }
+    return 0;
+}
+
+size_t lds_bytes_passB(int ny, int) {
+    switch (ny) {
+#define X(L) case L: return cols_lds<L>();
+        T2S_FOR_LENGTHS(X)
+#undef X
+    }
+    return 0;
+}
+
+int passB_columns(int ny, int) {
+    switch (ny) {
+#define X(L) case L: return colB<L>();
+        T2S_FOR_LENGTHS(X)
+#undef X
+    }
+    return 1;
+}
 
 hipError_t launch_passA(const ClassArgs& a, int s0, int count, const float2* src, int src_s0, int first,
                         PartialSrc gc, PartialSrc gp, hipStream_t st) {
     const dim3 grid(a.ny / kRowTile, a.K, count);
-    const size_t lds = lds_bytes_passA(a.nz);
     switch (a.nz) {
-#define X(L)                                                                                   \
-    case L:                                                                                    \
-        hipLaunchKernelGGL(k_passA<L>, grid, dim3(kThreads), lds, st, a, s0, src, src_s0, first, gc, gp); \
+#define X(L)                                                                                             \
+    case L:                                                                                              \
+        hipLaunchKernelGGL(k_passA<L>, grid, dim3(rows_threads<L>()), 0, st, a, s0, src, src_s0, first, gc, gp); \
         break;
         T2S_FOR_LENGTHS(X)
 #undef X
         default:
             return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_passB_L(const ClassArgs& a, int s0, int count, int mode, hipStream_t st) {
+    constexpr int W = colB<L>();
+    const dim3 grid((a.nz + W - 1) / W, a.C, count);
+    const dim3 block(W * RegGeom<L>::P);
+    if (mode == 1) {
+        hipLaunchKernelGGL(k_passB_inv<L>, grid, block, 0, st, a, s0);
+        return hipGetLastError();
+    }
+    switch (a.K) {
+        case 1: hipLaunchKernelGGL((k_passB<L, 1>), grid, block, 0, st, a, s0); break;
+        case 2: hipLaunchKernelGGL((k_passB<L, 2>), grid, block, 0, st, a, s0); break;
+        case 3: hipLaunchKernelGGL((k_passB<L, 3>), grid, block, 0, st, a, s0); break;
+        case 4: hipLaunchKernelGGL((k_passB<L, 4>), grid, block, 0, st, a, s0); break;
+        case 5: hipLaunchKernelGGL((k_passB<L, 5>), grid, block, 0, st, a, s0); break;
+        case 6: hipLaunchKernelGGL((k_passB<L, 6>), grid, block, 0, st, a, s0); break;
+        case 7: hipLaunchKernelGGL((k_passB<L, 7>), grid, block, 0, st, a, s0); break;
+        case 8: hipLaunchKernelGGL((k_passB<L, 8>), grid, block, 0, st, a, s0); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, hipStream_t st) {
-    const int W = passB_columns(a.ny, a.K);
-    const dim3 grid(a.nz / W, a.C, count);
-    const size_t lds = lds_bytes_passB(a.ny, a.K);
     switch (a.ny) {
-#define X(L)                                                                                 \
-    case L:                                                                                  \
-        if (mode == 0)                                                                       \
-            hipLaunchKernelGGL((k_passB<L, 0>), grid, dim3(kThreads), lds, st, a, s0, W);    \
-        else                                                                                 \
-            hipLaunchKernelGGL((k_passB<L, 1>), grid, dim3(kThreads), lds, st, a, s0, W);    \
-        break;
+#define X(L) case L: return launch_passB_L<L>(a, s0, count, mode, st);
         T2S_FOR_LENGTHS(X)
 #undef X
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float rho_add, float2* out,
                         int out_s0, hipStream_t st) {
     const dim3 grid(a.ny / kRowTile, a.K, count);
-    const size_t lds = lds_bytes_passA(a.nz);
     switch (a.nz) {
-#define X(L)                                                                                          \
-    case L:                                                                                           \
-        if (mode == 0)                                                                                \
-            hipLaunchKernelGGL((k_passC<L, 0>), grid, dim3(kThreads), lds, st, a, s0, rho_add, out, out_s0);  \
-        else                                                                                          \
-            hipLaunchKernelGGL((k_passC<L, 1>), grid, dim3(kThreads), lds, st, a, s0, rho_add, out, out_s0);  \
+#define X(L)                                                                                               \
+    case L:                                                                                                \
+        if (mode == 0)                                                                                     \
+            hipLaunchKernelGGL((k_passC<L, 0>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0); \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_passC<L, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0); \
         break;
         T2S_FOR_LENGTHS(X)
 #undef X
