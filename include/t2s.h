@@ -58,8 +58,11 @@ extern "C" {
 #define T2S_HOST 0
 #define T2S_DEVICE 1
 
-#define T2S_BATCHED 0   /* every launch covers all loaded slices of a shape class */
-#define T2S_PER_SLICE 1 /* one launch sequence per slice (baseline schedule)      */
+#define T2S_BATCHED 0        /* launches cover the slices of a class (per its schedule) */
+#define T2S_PER_SLICE 1      /* one launch sequence per slice (baseline schedule)       */
+#define T2S_BATCHED_GRAPH 2  /* T2S_BATCHED with one outer iteration captured in a HIP
+                                graph and replayed (falls back to T2S_BATCHED while
+                                kernel timing is enabled)                              */
 
 #define T2S_ALPHA 0
 #define T2S_Z 1
@@ -150,6 +153,21 @@ int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* a
  * iterations to read the per-slice residuals, and returns T2S_WNOTCONVERGED if a
  * slice reached n_outer without meeting tol. */
 int t2s_reconstruct(t2s_plan* plan, int mode, void* stream);
+
+/* Batching schedule of class `cls`: pass launches cover `chunk` slices (0 = all
+ * slices of the class) and are spread round-robin over `nstreams` (1..8)
+ * library-owned streams, so the pass intermediate of the slices in flight stays in
+ * the on-package cache between passes; the caller's stream waits for all of them.
+ * Same arithmetic for every schedule. */
+int t2s_set_schedule(t2s_plan* plan, int cls, int chunk, int nstreams);
+int t2s_get_schedule(const t2s_plan* plan, int cls, int* chunk, int* nstreams);
+
+/* Pick every class's schedule by timing `reps` CG steps of passes A/B/C per
+ * candidate (all slices at once; chunks of 32/16/8/4/2 slices over 1, 2 or 4
+ * streams) on the loaded slices, on `stream`.  Results are cached per process by
+ * (ny, nz, ncoils, K, slices, device architecture).  Solver state is untouched.
+ * Synchronises `stream`. */
+int t2s_autotune(t2s_plan* plan, int reps, void* stream);
 
 /* Copy out alpha, z, u or b0 (which = T2S_ALPHA / T2S_Z / T2S_U / T2S_ADJOINT) of
  * slices [first, first + count) as complex64 [count][K][ny][nz] into `out` (`mem`).

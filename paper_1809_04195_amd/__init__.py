@@ -32,6 +32,7 @@ T2S_HOST = 0
 T2S_DEVICE = 1
 T2S_BATCHED = 0
 T2S_PER_SLICE = 1
+T2S_BATCHED_GRAPH = 2
 T2S_ALPHA = 0
 T2S_Z = 1
 T2S_U = 2
@@ -116,6 +117,10 @@ _SIGS = {
     "t2s_profile_enable": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "t2s_profile_read": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
                          ctypes.c_int),
+    "t2s_set_schedule": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "t2s_get_schedule": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                         ctypes.c_int),
+    "t2s_autotune": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "t2s_block_shift": ([ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                          ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
 }
@@ -275,6 +280,20 @@ def t2s_profile_read(plan, kernel):
     n, ms = ctypes.c_int(), ctypes.c_double()
     _check(lib().t2s_profile_read(plan, kernel, ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def t2s_set_schedule(plan, cls, chunk, nstreams):
+    return _check(lib().t2s_set_schedule(plan, cls, chunk, nstreams))
+
+
+def t2s_get_schedule(plan, cls):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(lib().t2s_get_schedule(plan, cls, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def t2s_autotune(plan, reps=3, stream=None):
+    return _check(lib().t2s_autotune(plan, reps, _stream(stream)))
 
 
 def t2s_get_psi(plan, cls, K, ny, nz):

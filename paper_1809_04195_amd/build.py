@@ -37,7 +37,8 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(objdir, src + ".o")
         cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if lang == "c++":
-            cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [hipcc, f"--offload-arch={ARCH}", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c",
+                   os.path.join(CSRC, src), "-o", obj]
         _run(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"

@@ -3,7 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -47,8 +51,16 @@ struct ClassPlan {
            o_hist = 0, o_state = 0;
     std::vector<int> loaded;
     std::vector<int> outer_run, k_freeze, converged;
+    int chunk = 0;      // slices per pass launch (0: all slices of the class in one launch)
+    int nstreams = 1;   // streams the chunks are spread over
     ClassArgs args{};
 };
+
+// Autotuned schedules, shared by every plan of the process, keyed by the shape of
+// the class and the device architecture.
+using SchedKey = std::tuple<int, int, int, int, int, std::string>;   // ny, nz, C, K, slices, arch
+std::mutex g_sched_mu;
+std::map<SchedKey, std::pair<int, int>> g_sched;
 
 }  // namespace
 
@@ -62,6 +74,14 @@ struct Profiler {
 
 struct t2s_plan {
     Profiler prof;
+    std::vector<hipStream_t> aux;        // library-owned streams for chunked passes (default priority)
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
+    hipStream_t cap = nullptr;           // capture stream of the outer-iteration graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::string gkey;                    // schedule the graph was captured with
+    std::string arch;
     t2s_params prm{};
     std::vector<float> phi;
     std::vector<ClassPlan> cls;
@@ -174,14 +194,14 @@ struct TimedLaunch {
         if (p && p->on) {
             if (p->open[kind].size() > 4096) prof_drain(*p, kind);
             e0 = prof_event(*p);
-            if (e0) hipEventRecord(e0, st);
+            if (e0) (void)hipEventRecord(e0, st);
         }
     }
     ~TimedLaunch() {
         if (e0) {
             hipEvent_t e1 = prof_event(*p);
             if (e1) {
-                hipEventRecord(e1, st);
+                (void)hipEventRecord(e1, st);
                 p->open[kind].push_back({e0, e1});
             }
         }
@@ -191,6 +211,7 @@ struct TimedLaunch {
 thread_local Profiler* g_prof = nullptr;   // profiler of the plan being driven
 
 #define TIMED(kind) TimedLaunch timed_##__LINE__(g_prof, kind, st)
+#define TIMED_ON(kind, stream) TimedLaunch timed_on_##__LINE__(g_prof, kind, stream)
 
 PartialSrc rr_src(const ClassArgs& a, int buf) { return PartialSrc{a.rr + (size_t)buf * a.nrr, 2 * a.nrr, a.nrr}; }
 PartialSrc g0_src(const ClassArgs& a) { return PartialSrc{a.g0, a.nllr, a.nllr}; }
@@ -221,25 +242,56 @@ int run_normal(const ClassArgs& a, int s0, int count, const float2* src, int src
     return 0;
 }
 
-// one ADMM outer iteration k for slices [s0, s0 + count)
-int run_outer(const t2s_plan* plan, const ClassArgs& a, int s0, int count, int k, hipStream_t st) {
+// Passes A, B, C of CG step i for slices [s0, s0 + count): in one launch each, or in
+// chunks of `chunk` slices spread round-robin over `ns` library streams, so that the
+// pass intermediate of the slices in flight stays in the on-package cache between
+// the passes.  The caller's stream waits for every chunk before it continues.
+int run_passes(t2s_plan* plan, const ClassArgs& a, int s0, int count, int i, int chunk, int ns, hipStream_t st) {
+    const PartialSrc none{nullptr, 0, 0};
+    const PartialSrc gcA = (i == 0) ? none : rr_src(a, i % 2);
+    const PartialSrc gpA = (i == 0) ? none : (i == 1 ? g0_src(a) : rr_src(a, (i - 1) % 2));
+    if (chunk <= 0 || chunk >= count) {
+        chunk = count;
+        ns = 1;
+    }
+    const int nchunks = (count + chunk - 1) / chunk;
+    ns = std::max(1, std::min(ns, std::min(nchunks, (int)plan->aux.size())));
+    if (ns > 1) {
+        HIP_TRY(hipEventRecord(plan->ev_fork, st));
+        for (int j = 0; j < ns; ++j) HIP_TRY(hipStreamWaitEvent(plan->aux[j], plan->ev_fork, 0));
+    }
+    for (int q = 0; q < nchunks; ++q) {
+        hipStream_t sq = ns > 1 ? plan->aux[q % ns] : st;
+        const int c0 = s0 + q * chunk;
+        const int cn = std::min(chunk, s0 + count - c0);
+        {
+            TIMED_ON(T2S_KERNEL_PASS_A, sq);
+            HIP_CHECK_LAUNCH(t2s::launch_passA(a, c0, cn, a.r, 0, i == 0 ? 1 : 0, gcA, gpA, sq));
+        }
+        {
+            TIMED_ON(T2S_KERNEL_PASS_B, sq);
+            HIP_CHECK_LAUNCH(t2s::launch_passB(a, c0, cn, 0, sq));
+        }
+        {
+            TIMED_ON(T2S_KERNEL_PASS_C, sq);
+            HIP_CHECK_LAUNCH(t2s::launch_passC(a, c0, cn, 0, a.rho, a.w, 0, sq));
+        }
+    }
+    if (ns > 1) {
+        for (int j = 0; j < ns; ++j) {
+            HIP_TRY(hipEventRecord(plan->ev_join[j], plan->aux[j]));
+            HIP_TRY(hipStreamWaitEvent(st, plan->ev_join[j], 0));
+        }
+    }
+    return 0;
+}
+
+// one ADMM outer iteration for slices [s0, s0 + count) (the outer index lives in the
+// device-side slice state, so the same launch sequence serves every iteration)
+int run_outer(t2s_plan* plan, const ClassArgs& a, int s0, int count, int chunk, int ns, hipStream_t st) {
     const int ncg = plan->prm.n_cg;
     for (int i = 0; i < ncg; ++i) {
-        const PartialSrc none{nullptr, 0, 0};
-        const PartialSrc gcA = (i == 0) ? none : rr_src(a, i % 2);
-        const PartialSrc gpA = (i == 0) ? none : (i == 1 ? g0_src(a) : rr_src(a, (i - 1) % 2));
-        {
-            TIMED(T2S_KERNEL_PASS_A);
-            HIP_CHECK_LAUNCH(t2s::launch_passA(a, s0, count, a.r, 0, i == 0 ? 1 : 0, gcA, gpA, st));
-        }
-        {
-            TIMED(T2S_KERNEL_PASS_B);
-            HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, st));
-        }
-        {
-            TIMED(T2S_KERNEL_PASS_C);
-            HIP_CHECK_LAUNCH(t2s::launch_passC(a, s0, count, 0, a.rho, a.w, 0, st));
-        }
+        if (int e = run_passes(plan, a, s0, count, i, chunk, ns, st)) return e;
         const PartialSrc gcU = (i == 0) ? g0_src(a) : rr_src(a, i % 2);
         {
             TIMED(T2S_KERNEL_CG);
@@ -248,9 +300,73 @@ int run_outer(const t2s_plan* plan, const ClassArgs& a, int s0, int count, int k
     }
     {
         TIMED(T2S_KERNEL_LLR);
-        HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrAdmm, k, nullptr, nullptr, a.tau, 0, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrAdmm, 0, nullptr, nullptr, a.tau, 0, 0, st));
     }
-    HIP_CHECK_LAUNCH(t2s::launch_llr_finalize(a, s0, count, k, st));
+    HIP_CHECK_LAUNCH(t2s::launch_llr_finalize(a, s0, count, st));
+    return 0;
+}
+
+// one outer iteration of every class of the plan
+int run_outer_all(t2s_plan* plan, int mode, hipStream_t st) {
+    for (ClassPlan& c : plan->cls) {
+        if (mode == T2S_PER_SLICE) {
+            for (int s = 0; s < c.S; ++s)
+                if (int e = run_outer(plan, c.args, s, 1, 0, 1, st)) return e;
+        } else {
+            if (int e = run_outer(plan, c.args, 0, c.S, c.chunk, c.nstreams, st)) return e;
+        }
+    }
+    return 0;
+}
+
+std::string sched_signature(const t2s_plan* plan, int mode) {
+    std::string k = std::to_string(mode);
+    for (const ClassPlan& c : plan->cls) k += "/" + std::to_string(c.chunk) + "x" + std::to_string(c.nstreams);
+    return k;
+}
+
+int ensure_streams(t2s_plan* plan, int n) {
+    while ((int)plan->aux.size() < n) {
+        hipStream_t s = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        plan->aux.push_back(s);
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        plan->ev_join.push_back(e);
+    }
+    if (!plan->ev_fork) HIP_TRY(hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming));
+    if (!plan->cap) HIP_TRY(hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking));
+    return 0;
+}
+
+void drop_graph(t2s_plan* plan) {
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->gexec = nullptr;
+    plan->graph = nullptr;
+    plan->gkey.clear();
+}
+
+// Capture one outer iteration of every class into a graph (once per schedule).
+int ensure_graph(t2s_plan* plan, int mode) {
+    const std::string key = sched_signature(plan, mode);
+    if (plan->gexec && plan->gkey == key) return 0;
+    drop_graph(plan);
+    Profiler* saved = g_prof;
+    g_prof = nullptr;   // no timing events inside a captured graph
+    HIP_TRY(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeRelaxed));
+    int e = run_outer_all(plan, mode == T2S_BATCHED_GRAPH ? T2S_BATCHED : mode, plan->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(plan->cap, &g);
+    g_prof = saved;
+    if (e) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    if (ce != hipSuccess) return fail(T2S_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    plan->graph = g;
+    HIP_TRY(hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0));
+    plan->gkey = key;
     return 0;
 }
 
@@ -408,7 +524,7 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.o_g0 = take((size_t)c.S * c.nllr * 8);
         c.o_llr = take((size_t)c.S * c.nllr * 8 * 8);
         c.o_hist = take((size_t)c.S * plan->hist_len * 8 * 8);
-        c.o_state = take((size_t)c.S * 2 * 4);
+        c.o_state = take((size_t)c.S * 4 * 4);
     }
     plan->ws_bytes = off;
     *out = plan;
@@ -419,11 +535,16 @@ int t2s_plan_destroy(t2s_plan* plan) {
     if (plan) {
         for (int k = 0; k < T2S_KERNEL_COUNT; ++k)
             for (auto& pr : plan->prof.open[k]) {
-                hipEventDestroy(pr.first);
-                hipEventDestroy(pr.second);
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
             }
-        for (hipEvent_t e : plan->prof.pool) hipEventDestroy(e);
+        for (hipEvent_t e : plan->prof.pool) (void)hipEventDestroy(e);
         if (g_prof == &plan->prof) g_prof = nullptr;
+        drop_graph(plan);
+        for (hipStream_t x : plan->aux) (void)hipStreamDestroy(x);
+        for (hipEvent_t e : plan->ev_join) (void)hipEventDestroy(e);
+        if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+        if (plan->cap) (void)hipStreamDestroy(plan->cap);
     }
     delete plan;
     return 0;
@@ -473,6 +594,7 @@ int t2s_plan_bind_workspace(t2s_plan* plan, void* dev, size_t bytes, void* strea
                                               std::to_string(max_lds));
     }
     plan->ws = (char*)dev;
+    drop_graph(plan);   // kernel arguments of a captured graph point into the old workspace
     for (ClassPlan& c : plan->cls) {
         fill_args(plan, c);
         char* b = plan->ws;
@@ -483,7 +605,7 @@ int t2s_plan_bind_workspace(t2s_plan* plan, void* dev, size_t bytes, void* strea
         HIP_TRY(hipMemcpyAsync(b + c.o_rowptr, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(b + c.o_entt, c.ent_t.data(), c.ent_t.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(b + c.o_entp, c.ent_p.data(), c.ent_p.size() * 4, hipMemcpyHostToDevice, st));
-        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 0, -1, st));
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 0, -1, 0, st));
         std::fill(c.loaded.begin(), c.loaded.end(), 0);
     }
     HIP_TRY(hipStreamSynchronize(st));   // host tables are pageable: finish before returning
@@ -513,7 +635,7 @@ int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* s
     const ClassArgs& a = c.args;
     HIP_TRY(hipMemcpyAsync(a.sens + (size_t)first * c.C * N, sens, ns * 4, kind, st));
     if (nk) HIP_TRY(hipMemcpyAsync(a.ksp + (size_t)first * c.C * c.P, ksp, nk * 4, kind, st));
-    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, st));
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st));
     {
         g_prof = &plan->prof;
         TIMED(T2S_KERNEL_LOAD);
@@ -547,7 +669,7 @@ int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* a
     const ClassArgs& a = c.args;
     float2* xs = a.x + (size_t)first * K * c.ny * c.nz;
     HIP_TRY(hipMemcpyAsync(xs, alpha0, n * 4, mem == T2S_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
-    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, st));
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st));
     // r = b0 + rho z - (A^H A + rho) alpha0 with z = alpha0, u = 0  =>  r = b0 - A^H A alpha0
     if (int e = run_normal(a, first, count, a.x, 0, 0.0f, a.w, 0, st)) return e;
     HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, xs, 1, st));
@@ -557,7 +679,7 @@ int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* a
 
 int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
     if (!plan) return fail(T2S_EINVAL, "plan is NULL");
-    if (mode != T2S_BATCHED && mode != T2S_PER_SLICE) return fail(T2S_EINVAL, "bad mode");
+    if (mode != T2S_BATCHED && mode != T2S_PER_SLICE && mode != T2S_BATCHED_GRAPH) return fail(T2S_EINVAL, "bad mode");
     if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
     for (const ClassPlan& c : plan->cls)
         for (int s = 0; s < c.S; ++s)
@@ -567,31 +689,34 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
     g_prof = &plan->prof;
     const t2s_params& prm = plan->prm;
     const bool tolmode = prm.tol > 0;
+    int maxns = 1;
+    for (const ClassPlan& c : plan->cls) maxns = std::max(maxns, c.nstreams);
+    if (int e = ensure_streams(plan, maxns)) return e;
     for (ClassPlan& c : plan->cls) {
-        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, st));
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, 0, st));
         std::fill(c.outer_run.begin(), c.outer_run.end(), 0);
         std::fill(c.k_freeze.begin(), c.k_freeze.end(), -1);
         std::fill(c.converged.begin(), c.converged.end(), 0);
     }
-    auto outer_all = [&](int k) -> int {
-        for (ClassPlan& c : plan->cls) {
-            if (mode == T2S_BATCHED) {
-                if (int e = run_outer(plan, c.args, 0, c.S, k, st)) return e;
-            } else {
-                for (int s = 0; s < c.S; ++s)
-                    if (int e = run_outer(plan, c.args, s, 1, k, st)) return e;
-            }
+    // graphs carry no timing events: profiling falls back to eager launches
+    const bool use_graph = mode == T2S_BATCHED_GRAPH && !plan->prof.on;
+    if (use_graph) {
+        if (int e = ensure_graph(plan, mode)) return e;
+    }
+    auto outer_once = [&]() -> int {
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(plan->gexec, st));
+            return 0;
         }
-        return 0;
+        return run_outer_all(plan, mode == T2S_BATCHED_GRAPH ? T2S_BATCHED : mode, st);
     };
     int warn = 0;
     if (!tolmode) {
         for (int k = 0; k < prm.n_outer; ++k)
-            if (int e = outer_all(k)) return e;
+            if (int e = outer_once()) return e;
         for (ClassPlan& c : plan->cls) std::fill(c.outer_run.begin(), c.outer_run.end(), prm.n_outer);
     } else {
         // per-slice decisions every check_every outer iterations (see t2s.h)
-        std::vector<std::vector<double>> res(plan->cls.size());
         std::vector<std::vector<int>> active(plan->cls.size());
         for (size_t ci = 0; ci < plan->cls.size(); ++ci) active[ci].assign(plan->cls[ci].S, 1);
         std::vector<double> hbuf;
@@ -600,7 +725,7 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
         while (k < prm.n_outer && any) {
             const int kend = std::min(prm.n_outer, k + prm.check_every);
             for (; k < kend; ++k)
-                if (int e = outer_all(k)) return e;
+                if (int e = outer_once()) return e;
             HIP_TRY(hipStreamSynchronize(st));
             any = false;
             for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
@@ -624,12 +749,12 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
                                             prm.rho, &rpo, &rdo);
                         if (r > (1.0 - prm.freeze_stall) * std::max(rpo, rdo)) {
                             c.k_freeze[s] = k - 1;
-                            HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 1, k - 1, st));
+                            HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 1, k - 1, -1, st));
                         }
                     }
                     if (stop) {
                         active[ci][s] = 0;
-                        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 0, c.k_freeze[s], st));
+                        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 0, c.k_freeze[s], -1, st));
                     } else {
                         any = true;
                     }
@@ -642,6 +767,91 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
     }
     plan->reconstructed = true;
     if (warn) return fail(warn, "tolerance not met by n_outer for some slices");
+    return 0;
+}
+
+int t2s_set_schedule(t2s_plan* plan, int cls, int chunk, int nstreams) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
+    if (chunk < 0 || nstreams < 1 || nstreams > 8) return fail(T2S_EINVAL, "chunk must be >= 0, nstreams in [1, 8]");
+    plan->cls[cls].chunk = chunk;
+    plan->cls[cls].nstreams = nstreams;
+    return 0;
+}
+
+int t2s_get_schedule(const t2s_plan* plan, int cls, int* chunk, int* nstreams) {
+    if (!plan || !chunk || !nstreams) return fail(T2S_EINVAL, "NULL argument");
+    if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
+    *chunk = plan->cls[cls].chunk;
+    *nstreams = plan->cls[cls].nstreams;
+    return 0;
+}
+
+int t2s_autotune(t2s_plan* plan, int reps, void* stream) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    for (const ClassPlan& c : plan->cls)
+        for (int s = 0; s < c.S; ++s)
+            if (!c.loaded[s]) return fail(T2S_ESTATE, "autotuning runs on loaded slices");
+    if (reps < 1) reps = 3;
+    hipStream_t st = (hipStream_t)stream;
+    Profiler* saved = g_prof;
+    g_prof = nullptr;
+    if (int e = ensure_streams(plan, 4)) return e;
+    if (plan->arch.empty()) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        plan->arch = prop.gcnArchName;
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    for (ClassPlan& c : plan->cls) {
+        const SchedKey key{c.ny, c.nz, c.C, plan->prm.K, c.S, plan->arch};
+        {
+            std::lock_guard<std::mutex> lk(g_sched_mu);
+            auto it = g_sched.find(key);
+            if (it != g_sched.end()) {
+                c.chunk = it->second.first;
+                c.nstreams = it->second.second;
+                continue;
+            }
+        }
+        // candidates: everything in one launch, or chunks of 32..2 slices over 1, 2 or 4 streams
+        std::vector<std::pair<int, int>> cands{{0, 1}};
+        for (int ch : {32, 16, 8, 4, 2})
+            if (ch < c.S)
+                for (int ns : {1, 2, 4}) cands.push_back({ch, ns});
+        float best = 1e30f;
+        std::pair<int, int> pick{0, 1};
+        for (auto cand : cands) {
+            // one warm-up, then `reps` timed CG steps (passes only: the solver state is untouched)
+            for (int r = 0; r <= reps; ++r) {
+                if (r == 1) HIP_TRY(hipEventRecord(e0, st));
+                if (int e = run_passes(plan, c.args, 0, c.S, 0, cand.first, cand.second, st)) {
+                    g_prof = saved;
+                    return e;
+                }
+            }
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                pick = cand;
+            }
+        }
+        c.chunk = pick.first;
+        c.nstreams = pick.second;
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_sched[key] = pick;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_prof = saved;
     return 0;
 }
 
@@ -699,7 +909,7 @@ int t2s_apply_normal(t2s_plan* plan, int cls, int first, int count, const void* 
         if (!c.loaded[first + i]) return fail(T2S_ESTATE, "slice not loaded");
     hipStream_t st = (hipStream_t)stream;
     g_prof = &plan->prof;
-    HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, first, count, 1, -1, st));
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, first, count, 1, -1, -1, st));
     return run_normal(c.args, first, count, (const float2*)in, first, rho_add, (float2*)out, first, st);
 }
 

@@ -55,7 +55,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
-__device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[2 * s] != 0; }
+__device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[4 * s] != 0; }
 
 __host__ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
     uint64_t z = x + 0x9E3779B97F4A7C15ull;
@@ -554,8 +554,10 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
 
     int sy = sy_arg, sz = sz_arg;
     if (MODE == kLlrAdmm) {
-        const int fk = a.state[2 * s + 1];
-        const uint64_t kk = (uint64_t)(fk >= 0 ? fk : kouter);
+        // outer index from the device counter (so an outer iteration can be replayed
+        // from a captured graph); a frozen shift overrides it
+        const int fk = a.state[4 * s + 1];
+        const uint64_t kk = (uint64_t)(fk >= 0 ? fk : a.state[4 * s + 2]);
         const uint64_t h = sm64(sm64(sm64(a.seed) ^ (uint64_t)(a.gbase + s)) ^ kk);
         sy = (int)((h & 0xFFFFFFFFull) % (uint64_t)B);
         sz = (int)((h >> 32) % (uint64_t)B);
@@ -692,14 +694,18 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
     }
 }
 
-__global__ void k_llr_finalize(ClassArgs a, int s0, int k) {
+__global__ void k_llr_finalize(ClassArgs a, int s0) {
     const int s = s0 + blockIdx.x;
     if (!slice_active(a, s)) return;
     const int j = threadIdx.x;
-    if (j >= 6) return;
-    double acc = 0.0;
-    for (int i = 0; i < a.nllr; ++i) acc += a.llr[((size_t)s * a.nllr + i) * 8 + j];
-    a.hist[((size_t)s * a.hist_len + k) * 8 + j] = acc;
+    const int k = a.state[4 * s + 2];
+    if (j < 6 && k < a.hist_len) {
+        double acc = 0.0;
+        for (int i = 0; i < a.nllr; ++i) acc += a.llr[((size_t)s * a.nllr + i) * 8 + j];
+        a.hist[((size_t)s * a.hist_len + k) * 8 + j] = acc;
+    }
+    __syncthreads();
+    if (j == 0) a.state[4 * s + 2] = k + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -866,21 +872,23 @@ hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, co
     }
 }
 
-__global__ void k_set_state(ClassArgs a, int s0, int count, int active, int frozen) {
+__global__ void k_set_state(ClassArgs a, int s0, int count, int active, int frozen, int kreset) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) {
-        a.state[2 * (s0 + i)] = active;
-        a.state[2 * (s0 + i) + 1] = frozen;
+        a.state[4 * (s0 + i)] = active;
+        a.state[4 * (s0 + i) + 1] = frozen;
+        if (kreset >= 0) a.state[4 * (s0 + i) + 2] = kreset;
     }
 }
 
-hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, hipStream_t st) {
-    hipLaunchKernelGGL(k_set_state, dim3((count + 63) / 64), dim3(64), 0, st, a, s0, count, active, frozen);
+hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, int kreset,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_set_state, dim3((count + 63) / 64), dim3(64), 0, st, a, s0, count, active, frozen, kreset);
     return hipGetLastError();
 }
 
-hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, int k, hipStream_t st) {
-    hipLaunchKernelGGL(k_llr_finalize, dim3(count), dim3(64), 0, st, a, s0, k);
+hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_llr_finalize, dim3(count), dim3(64), 0, st, a, s0);
     return hipGetLastError();
 }
 

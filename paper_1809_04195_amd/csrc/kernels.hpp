@@ -43,7 +43,7 @@ struct ClassArgs {
     double* g0;                  // [S][nllr]   <r, r> at the start of an outer iteration
     double* llr;                 // [S][nllr][8] residual partial sums of the z-step
     double* hist;                // [S][hist_len][8] per-outer residual sums
-    int* state;                  // [S][2]: active flag, frozen outer index (-1: none)
+    int* state;                  // [S][4]: active flag, frozen outer index (-1: none), outer counter, spare
 };
 
 // LLR kernel flavours
@@ -69,14 +69,15 @@ hipError_t launch_project(const ClassArgs& a, int s0, int count, hipStream_t st)
 hipError_t launch_cg_update(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st);
 // x = z = alpha0 (or 0), u = 0, r = b0 - (sub_w ? w : 0); partial <r, r> into g0
 hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alpha0, int sub_w, hipStream_t st);
-// ADMM z/u/r update with the shift of outer iteration k (mode kLlrAdmm), or
-// out = prox(in) at explicit shift (mode kLlrProx)
+// ADMM z/u/r update with the shift of the slice's outer counter (mode kLlrAdmm;
+// k unused), or out = prox(in) at the explicit shift (mode kLlrProx)
 hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
                       float tau, int sy, int sz, hipStream_t st);
-// state[s] = (active, frozen) for slices [s0, s0 + count)
-hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, hipStream_t st);
-// hist[s][k] = sum of the LLR partials of slice s
-hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, int k, hipStream_t st);
+// state[s] = (active, frozen[, counter = kreset if kreset >= 0]) for slices [s0, s0 + count)
+hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, int kreset,
+                            hipStream_t st);
+// hist[s][counter] = sum of the LLR partials of slice s; counter += 1
+hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, hipStream_t st);
 
 bool fft_supported(int L);
 size_t lds_bytes_passA(int nz);

@@ -217,3 +217,63 @@ def test_nonfinite_host_input_rejected():
         plan.load(0, 0, sens, bad)
     assert ei.value.code == T.T2S_ENONFINITE
     plan.close()
+
+
+def _run_sched(phi, sens, masks, ksp, mode, sched=None, reps=1, between=None):
+    S = sens.shape[0]
+    plan = _plan(phi, [dict(ny=64, nz=64, ncoils=sens.shape[1], nslices=S, masks=masks)], lam=0.05, rho=0.1,
+                 n_outer=4, n_cg=3, seed=17)
+    if sched is not None:
+        T.t2s_set_schedule(plan.handle, 0, *sched)
+    outs = []
+    for r in range(reps):
+        plan.load(0, 0, sens, ksp)
+        plan.reconstruct(mode)
+        outs.append(plan.read(0, 0, S))
+        if between is not None:
+            between(plan)
+    plan.close()
+    return outs
+
+
+def test_chunked_schedules_bitwise():
+    _say("chunked pass launches over 1-3 streams vs one launch per pass")
+    phi, sens, masks, ksp = random_problem(31, 64, 64, 3, 8, 3, S=5, frac=0.3)
+    ref = _run_sched(phi, sens, masks, ksp, T.T2S_BATCHED)[0]
+    for sched in [(2, 1), (2, 2), (1, 3), (3, 2), (4, 4)]:
+        got = _run_sched(phi, sens, masks, ksp, T.T2S_BATCHED, sched)[0]
+        assert np.array_equal(got, ref), sched
+
+
+def test_graph_replay_matches_eager():
+    import torch
+    _say("hipGraph replay of the outer iteration vs eager launches, 3 replays with eager work between")
+    phi, sens, masks, ksp = random_problem(32, 64, 64, 3, 8, 3, S=4, frac=0.3)
+    ref = _run_sched(phi, sens, masks, ksp, T.T2S_BATCHED)[0]
+
+    def eager_work(plan):
+        a = torch.ones((1, 3, 64, 64), dtype=torch.complex64, device="cuda")
+        o = torch.empty_like(a)
+        T.t2s_apply_normal(plan.handle, 0, 0, 1, a, o, 0.0)
+        torch.cuda.synchronize()
+
+    for sched in [None, (2, 2)]:
+        outs = _run_sched(phi, sens, masks, ksp, T.T2S_BATCHED_GRAPH, sched, reps=3, between=eager_work)
+        for i, got in enumerate(outs):
+            assert np.array_equal(got, ref), (sched, i)
+
+
+def test_autotune_schedule_valid_and_exact():
+    _say("autotuner picks a schedule; results unchanged")
+    phi, sens, masks, ksp = random_problem(33, 64, 64, 3, 8, 3, S=6, frac=0.3)
+    ref = _run_sched(phi, sens, masks, ksp, T.T2S_BATCHED)[0]
+    plan = _plan(phi, [dict(ny=64, nz=64, ncoils=3, nslices=6, masks=masks)], lam=0.05, rho=0.1, n_outer=4, n_cg=3,
+                 seed=17)
+    plan.load(0, 0, sens, ksp)
+    T.t2s_autotune(plan.handle, 2)
+    ch, ns = T.t2s_get_schedule(plan.handle, 0)
+    _say(f"  picked chunk={ch} streams={ns}")
+    assert 0 <= ch <= 6 and 1 <= ns <= 4
+    plan.reconstruct(T.T2S_BATCHED_GRAPH)
+    assert np.array_equal(plan.read(0, 0, 6), ref)
+    plan.close()
