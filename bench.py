@@ -102,7 +102,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=1, help="workload id (1: 320 x 256^2 volume)")
-    ap.add_argument("--mode", choices=["batched", "per_slice"], default="batched")
+    ap.add_argument("--mode", choices=["batched", "graph", "per_slice"], default="batched",
+                    help="launch schedule; 'graph' replays a captured outer iteration (no per-kernel events)")
+    ap.add_argument("--schedule", type=str, default="auto",
+                    help="'auto' (autotuner), or CHUNK,STREAMS applied to every shape class")
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(16, cores))")
     ap.add_argument("--cpu-outer", type=int, default=6, help="outer iterations of each oracle slice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -150,8 +153,20 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         log("copy probe: 1 GiB read + 1 GiB write")
-    mode = T.T2S_BATCHED if args.mode == "batched" else T.T2S_PER_SLICE
+    mode = {"batched": T.T2S_BATCHED, "graph": T.T2S_BATCHED_GRAPH, "per_slice": T.T2S_PER_SLICE}[args.mode]
     stream = torch.cuda.current_stream()
+    for ci in range(len(classes)):
+        T.t2s_load_slices(plan.handle, ci, 0, classes[ci].nslices, dsens[ci], dksp[ci], stream)
+    if args.schedule == "auto":
+        t0 = time.perf_counter()
+        T.t2s_autotune(plan.handle, 3, stream)
+        log(f"autotune {time.perf_counter() - t0:.1f} s")
+    else:
+        ch, ns = (int(v) for v in args.schedule.split(","))
+        for ci in range(len(classes)):
+            T.t2s_set_schedule(plan.handle, ci, ch, ns)
+    scheds = [T.t2s_get_schedule(plan.handle, ci) for ci in range(len(classes))]
+    log(f"schedules (chunk, streams): {scheds}")
 
     def step():
         for ci in range(len(classes)):
@@ -162,7 +177,7 @@ def main():
         step()
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
-    T.t2s_profile_enable(plan.handle, True)
+    T.t2s_profile_enable(plan.handle, mode != T.T2S_BATCHED_GRAPH)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -177,30 +192,38 @@ def main():
     ms_per_step = elapsed * 1000.0 / args.steps
     value = n_slices / (ms_per_step / 1000.0)
 
-    # dominant kernel: largest summed event time
+    # per kernel family: algorithmic bytes moved during the timed region / summed event time
+    counts = {"pass_a": cfg["n_cg"], "pass_b": cfg["n_cg"], "pass_c": cfg["n_cg"], "cg_update": cfg["n_cg"],
+              "llr_admm": 1}
     kern = {}
     for name, (n, ms) in prof.items():
         if n == 0:
             continue
-        per = []
-        for c in classes:
-            b = alg_bytes_per_slice(name, c.ny, c.nz, c.ncoils, phi.shape[1], cfg["n_cg"])
-            per.append(None if b is None else b * c.nslices)
-        nb = None if any(p is None for p in per) else sum(per) / len(classes)
+        tb = None
+        if name in counts:
+            tb = sum(alg_bytes_per_slice(name, c.ny, c.nz, c.ncoils, phi.shape[1], cfg["n_cg"]) * c.nslices
+                     for c in classes) * counts[name] * cfg["n_outer"] * args.steps
         kern[name] = dict(launches=n, total_ms=ms, avg_ms=ms / n,
-                          alg_bytes_per_launch=nb,
-                          achieved_gbs=(nb / (ms / n) / 1e6) if nb else None)
-    dom = max((k for k in kern if kern[k]["alg_bytes_per_launch"]), key=lambda k: kern[k]["total_ms"])
-    kd = kern[dom]
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        tr = json.load(open(args.traffic))
-        traffic = tr.get(dom)
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(kd["achieved_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
-                    avg_launch_ms=round(kd["avg_ms"], 4), alg_bytes_per_launch=int(kd["alg_bytes_per_launch"]))
-    # whole-solve algorithmic bandwidth (all kernel families with a byte model)
-    tot_bytes = sum(k["alg_bytes_per_launch"] * k["launches"] for k in kern.values() if k["alg_bytes_per_launch"])
+                          alg_bytes_per_launch=(tb / n) if tb else None,
+                          achieved_gbs=(tb / (ms * 1e6)) if tb else None)
+    roofline = None
+    if kern:
+        dom = max((k for k in kern if kern[k]["alg_bytes_per_launch"]), key=lambda k: kern[k]["total_ms"])
+        kd = kern[dom]
+        traffic = None
+        if args.traffic and os.path.exists(args.traffic):
+            tr = json.load(open(args.traffic))
+            traffic = tr.get(dom)
+        roofline = dict(bound="hbm", kernel=dom, achieved=round(kd["achieved_gbs"], 1), peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
+                        avg_launch_ms=round(kd["avg_ms"], 4), alg_bytes_per_launch=int(kd["alg_bytes_per_launch"]))
+    # whole-solve algorithmic bandwidth (solver kernels with a byte model, per slice and outer iteration)
+    per_outer = 0.0
+    for c in classes:
+        for name, mult in (("pass_a", cfg["n_cg"]), ("pass_b", cfg["n_cg"]), ("pass_c", cfg["n_cg"]),
+                           ("cg_update", cfg["n_cg"]), ("llr_admm", 1)):
+            per_outer += mult * c.nslices * alg_bytes_per_slice(name, c.ny, c.nz, c.ncoils, phi.shape[1], cfg["n_cg"])
+    tot_bytes = per_outer * cfg["n_outer"] * args.steps
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -219,7 +242,8 @@ def main():
                    "classes": [f"{c.nslices}x{c.ny}x{c.nz}c{c.ncoils}" for c in classes],
                    "T": int(phi.shape[0]), "K": int(phi.shape[1]), "outer": cfg["n_outer"], "cg": cfg["n_cg"],
                    "block": cfg["block"], "lambda": cfg["lam"], "rho": cfg["rho"], "mode": args.mode,
-                   "step": "load_slices(device inputs) + reconstruct"},
+                   "step": "load_slices(device inputs) + reconstruct",
+                   "schedules": [list(x) for x in scheds]},
         "roofline": roofline,
         "solver_alg_gbs": round(tot_bytes / (elapsed * 1e9), 1),
         "kernels": {k: dict(launches=v["launches"], avg_ms=round(v["avg_ms"], 4),
