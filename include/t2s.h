@@ -220,6 +220,48 @@ int t2s_profile_read(t2s_plan* plan, int kernel, int* launches, double* total_ms
  * global slice index g (class-major order) and outer iteration k.  Host only. */
 int t2s_block_shift(uint64_t seed, int g, int k, int b, int* sy, int* sz);
 
+/* ---- Learned warm start: U-Net on the zero-filled adjoint (bf16 matrix cores) ----
+ *
+ * Not part of the paper's method (its reconstruction is plain iterative); it
+ * predicts the solver's output alpha from b0 = A^H y so that ADMM starts closer to
+ * its fixed point, and the ADMM that follows still runs to the same residual.
+ * Network: input b0 of each slice packed as 2K real channels (Re, Im per
+ * coefficient image) divided by s = max |b0| of the slice; `levels` levels of two
+ * 3x3 convolutions + ReLU with base, 2 base, 4 base ... channels, 2x2 max-pool
+ * down, 2x2 stride-2 transposed convolution up with skip concatenation; final 1x1
+ * convolution and a global residual; output times s.  NHWC bf16 activations, fp32
+ * accumulation and fp32 master weights; parameters packed per layer in forward order
+ * as W[KH][KW][Cout][Cin] followed by bias[Cout] (a transposed convolution stores
+ * W[2][2][Cout][Cin]). */
+typedef struct t2s_unet t2s_unet;
+
+/* Describe a network for batches of up to max_batch slices of H x W (H, W divisible
+ * by 2^(levels-1)).  No HIP call.  Errors: T2S_EINVAL, T2S_ESHAPE. */
+int t2s_unet_create(int K, int base, int levels, int max_batch, int H, int W, t2s_unet** out);
+int t2s_unet_destroy(t2s_unet* net);
+int t2s_unet_param_count(const t2s_unet* net, size_t* count);
+int t2s_unet_workspace_bytes(const t2s_unet* net, size_t* bytes);
+/* Bind caller-owned device memory (256-byte aligned) and clear it. */
+int t2s_unet_bind_workspace(t2s_unet* net, void* device_ptr, size_t bytes, void* stream);
+/* Load (host fp32, packed) / read back the parameters; loading resets Adam.  Synchronous. */
+int t2s_unet_set_params(t2s_unet* net, const float* params, void* stream);
+int t2s_unet_get_params(t2s_unet* net, float* params, void* stream);
+/* alpha0 = s (x + net(x)) with x = pack(b0) / s; b0, alpha0: device complex64
+ * [B][K][H][W], 1 <= B <= max_batch.  Asynchronous. */
+int t2s_unet_forward(t2s_unet* net, const void* b0, void* alpha0, int B, void* stream);
+/* One Adam step (lr; beta 0.9 / 0.999, eps 1e-8) on the mean squared error between
+ * x + net(x) and target / s (target: device complex64 [B][K][H][W]).  If `loss` is not
+ * NULL the loss before the step is returned (synchronises `stream`). */
+int t2s_unet_train_step(t2s_unet* net, const void* b0, const void* target, int B, float lr, double* loss,
+                        void* stream);
+/* Verification entry: loss and packed parameter gradient for host fp32 inputs x and
+ * targets t, both [B][H][W][2K] (already normalised).  Synchronous. */
+int t2s_unet_loss_grad(t2s_unet* net, const float* x, const float* t, int B, double* loss, float* grad,
+                       void* stream);
+/* One 16x16x16 bf16 matrix-core product D = A B (host fp32 row-major, rounded to bf16
+ * on input) -- a check of the lane layout the convolution kernels assume. */
+int t2s_unet_mfma_probe(const float* A, const float* B, float* D);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,6 +121,23 @@ _SIGS = {
     "t2s_get_schedule": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
                          ctypes.c_int),
     "t2s_autotune": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "t2s_unet_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                         ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "t2s_unet_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "t2s_unet_param_count": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "t2s_unet_workspace_bytes": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "t2s_unet_bind_workspace": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "t2s_unet_set_params": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p], ctypes.c_int),
+    "t2s_unet_get_params": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p], ctypes.c_int),
+    "t2s_unet_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
+                         ctypes.c_int),
+    "t2s_unet_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
+                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p], ctypes.c_int),
+    "t2s_unet_loss_grad": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                            ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
+                            ctypes.c_void_p], ctypes.c_int),
+    "t2s_unet_mfma_probe": ([ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "t2s_block_shift": ([ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                          ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
 }
@@ -353,6 +370,84 @@ class Plan:
     def close(self):
         if self.handle is not None:
             t2s_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- warm-start network ---------------------------------------------------------------
+
+_FP = ctypes.POINTER(ctypes.c_float)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(_FP)
+
+
+def t2s_unet_mfma_probe(A, B):
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    D = np.empty((16, 16), dtype=np.float32)
+    _check(lib().t2s_unet_mfma_probe(_fptr(A), _fptr(B), _fptr(D)))
+    return D
+
+
+class UNet:
+    """The warm-start network (kernels in libt2s.so) with a torch-allocated workspace."""
+
+    def __init__(self, K, base=32, levels=4, max_batch=16, H=256, W=256, device="cuda"):
+        import torch
+        self.K, self.base, self.levels, self.max_batch, self.H, self.W = K, base, levels, max_batch, H, W
+        h = ctypes.c_void_p()
+        _check(lib().t2s_unet_create(K, base, levels, max_batch, H, W, ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_size_t()
+        _check(lib().t2s_unet_param_count(h, ctypes.byref(n)))
+        self.nparams = n.value
+        _check(lib().t2s_unet_workspace_bytes(h, ctypes.byref(n)))
+        self.nbytes = n.value
+        self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        base_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        _check(lib().t2s_unet_bind_workspace(h, base_ptr, self.nbytes, _stream(None)))
+
+    def set_params(self, params, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {p.size}")
+        _check(lib().t2s_unet_set_params(self.handle, _fptr(p), _stream(stream)))
+
+    def get_params(self, stream=None):
+        p = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().t2s_unet_get_params(self.handle, _fptr(p), _stream(stream)))
+        return p
+
+    def forward(self, b0, out, stream=None):
+        """b0, out: device complex64 tensors [B, K, H, W]."""
+        _check(lib().t2s_unet_forward(self.handle, _ptr(b0), _ptr(out), b0.shape[0], _stream(stream)))
+        return out
+
+    def train_step(self, b0, target, lr, want_loss=False, stream=None):
+        loss = ctypes.c_double()
+        _check(lib().t2s_unet_train_step(self.handle, _ptr(b0), _ptr(target), b0.shape[0], lr,
+                                         ctypes.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def loss_grad(self, x, t, stream=None):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(lib().t2s_unet_loss_grad(self.handle, _fptr(x), _fptr(t), x.shape[0], ctypes.byref(loss), _fptr(g),
+                                        _stream(stream)))
+        return loss.value, g
+
+    def close(self):
+        if self.handle is not None:
+            lib().t2s_unet_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -33,7 +33,7 @@ def build(verbose: bool = True) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    for src, lang in (("kernels.hip", "hip"), ("api.cpp", "c++")):
+    for src, lang in (("kernels.hip", "hip"), ("unet.hip", "hip"), ("api.cpp", "c++")):
         obj = os.path.join(objdir, src + ".o")
         cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if lang == "c++":

@@ -64,6 +64,10 @@ std::map<SchedKey, std::pair<int, int>> g_sched;
 
 }  // namespace
 
+namespace t2s {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace t2s
+
 struct Profiler {
     bool on = false;
     std::vector<hipEvent_t> pool;             // free events

@@ -169,3 +169,18 @@ def test_host_inputs_nonfinite_rejected_before_gpu():
     a0 = np.zeros((1, 3, 32, 48), np.complex64)
     assert T.lib().t2s_set_initial(h, 0, 0, 1, a0.ctypes.data, 0, None) == T.T2S_ESTATE
     T.t2s_plan_destroy(h)
+
+
+def test_unet_create_validation_and_sizes():
+    L = T.lib()
+    h = ctypes.c_void_p()
+    assert L.t2s_unet_create(0, 32, 4, 1, 256, 256, ctypes.byref(h)) == T.T2S_EINVAL
+    assert L.t2s_unet_create(4, 32, 4, 1, 100, 256, ctypes.byref(h)) == T.T2S_ESHAPE
+    assert L.t2s_unet_create(4, 32, 4, 16, 256, 256, ctypes.byref(h)) == 0
+    n = ctypes.c_size_t()
+    assert L.t2s_unet_param_count(h, ctypes.byref(n)) == 0
+    from oracle import unet as U
+    assert n.value == U.param_count(8, 32, 4)
+    assert L.t2s_unet_workspace_bytes(h, ctypes.byref(n)) == 0 and n.value > 0
+    assert L.t2s_unet_bind_workspace(h, None, 0, None) == T.T2S_ENOMEM
+    assert L.t2s_unet_destroy(h) == 0

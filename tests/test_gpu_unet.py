@@ -1,0 +1,126 @@
+"""GPU checks of the warm-start network kernels against the FP64 oracle.
+
+BF16 activations and weights with FP32 accumulation: per-tensor relative L2 within
+2e-2 of the FP64 result and cosine similarity >= 0.999 (gradients: see below).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1809_04195_amd as T
+from oracle import unet as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu(gpu):
+    return gpu
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def bf16_round(a):
+    a = np.asarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32)
+
+
+def test_mfma_lane_layout():
+    rng = np.random.default_rng(0)
+    A = rng.integers(-8, 9, (16, 16)).astype(np.float32) / 8
+    B = rng.integers(-8, 9, (16, 16)).astype(np.float32) / 4
+    D = T.t2s_unet_mfma_probe(A, B)
+    assert np.array_equal(D, (A.astype(np.float64) @ B).astype(np.float32))
+
+
+def _tiny(seed, K=2, base=8, levels=3, H=16, W=16, B=2):
+    rng = np.random.default_rng(seed)
+    params = U.init_params(2 * K, base, levels, seed=seed, final_scale=1.0)
+    params = params + 0.02 * rng.standard_normal(params.size).astype(np.float32)
+    x = rng.standard_normal((B, H, W, 2 * K)).astype(np.float32)
+    t = rng.standard_normal((B, H, W, 2 * K)).astype(np.float32)
+    return params, x, t
+
+
+def cos(a, b):
+    return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+def test_forward_matches_oracle():
+    import torch
+    K, base, levels, H, W, B = 2, 8, 3, 16, 16, 2
+    params, _, _ = _tiny(1, K, base, levels, H, W, B)
+    rng = np.random.default_rng(3)
+    b0 = (rng.standard_normal((B, K, H, W)) + 1j * rng.standard_normal((B, K, H, W))).astype(np.complex64)
+    net = T.UNet(K, base, levels, max_batch=B, H=H, W=W)
+    net.set_params(params)
+    d_in = torch.from_numpy(b0).cuda()
+    d_out = torch.empty_like(d_in)
+    net.forward(d_in, d_out)
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy()
+    for s in range(B):
+        scale = np.abs(b0[s]).max()
+        x = U.pack(b0[s].astype(np.complex128), scale)[None]
+        out, _ = U.forward(params.astype(np.float64), x, base, levels)
+        ref_net = out[0] - x[0]
+        got_net = U.pack(got[s].astype(np.complex128), scale) - x[0]
+        e = np.linalg.norm(got_net - ref_net) / np.linalg.norm(ref_net)
+        c = cos(got_net.ravel(), ref_net.ravel())
+        _say(f"  slice {s}: net(x) rel L2 {e:.3e} cosine {c:.6f}")
+        assert e < 2e-2 and c > 0.999
+    net.close()
+
+
+def test_gradient_matches_oracle():
+    K, base, levels, H, W, B = 2, 8, 3, 16, 16, 2
+    params, x, t = _tiny(2, K, base, levels, H, W, B)
+    net = T.UNet(K, base, levels, max_batch=B, H=H, W=W)
+    net.set_params(params)
+    loss, g = net.loss_grad(x, t)
+    rloss, rg = U.loss_and_grad(params.astype(np.float64), x, t, base, levels)
+    _say(f"  loss gpu {loss:.6f} oracle {rloss:.6f}")
+    assert abs(loss - rloss) < 2e-2 * rloss
+    off = 0
+    worst = []
+    for name, kind, k, ci, co in U.layer_specs(2 * K, base, levels):
+        for part, n in (("W", k * k * ci * co), ("b", co)):
+            a, b = g[off:off + n].astype(np.float64), rg[off:off + n]
+            off += n
+            e = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
+            c = cos(a, b)
+            worst.append((e, c, name + part))
+            _say(f"  {name}.{part}: rel L2 {e:.3e} cosine {c:.5f}")
+    # whole-vector agreement, and every tensor pointing the same way
+    e_all = np.linalg.norm(g - rg) / np.linalg.norm(rg)
+    assert e_all < 3e-2, e_all
+    assert min(c for _, c, _ in worst) > 0.995
+    assert cos(g.astype(np.float64), rg) > 0.999
+    net.close()
+
+
+def test_training_reduces_loss():
+    import torch
+    K, base, levels, H, W, B = 2, 8, 3, 32, 32, 4
+    rng = np.random.default_rng(5)
+    params = U.init_params(2 * K, base, levels, seed=5)
+    net = T.UNet(K, base, levels, max_batch=B, H=H, W=W)
+    net.set_params(params)
+    # target: a smoothed, rescaled copy of the input (learnable by a small conv net)
+    b0 = (rng.standard_normal((B, K, H, W)) + 1j * rng.standard_normal((B, K, H, W))).astype(np.complex64)
+    sm = 0.25 * (b0 + np.roll(b0, 1, 2) + np.roll(b0, 1, 3) + np.roll(b0, (1, 1), (2, 3)))
+    tgt = (1.5 * sm).astype(np.complex64)
+    db0 = torch.from_numpy(b0).cuda()
+    dt = torch.from_numpy(tgt).cuda()
+    losses = [net.train_step(db0, dt, 3e-3, want_loss=True) for _ in range(60)]
+    _say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.3 * losses[0]
+    assert np.all(np.isfinite(net.get_params()))
+    net.close()
