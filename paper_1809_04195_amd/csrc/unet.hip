@@ -141,14 +141,13 @@ __global__ __launch_bounds__(kNT) void k_conv(ConvArgs a) {
             } else {
                 base = (size_t)(p_w + j * 16 + r16) * a.ldo + a.co_off + co0;
             }
+            const int nr = min(4, a.cout - co0);
             if (a.out_f32) {
                 float* o = (float*)a.out + base;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) o[r] = v[r];
+                for (int r = 0; r < nr; ++r) o[r] = v[r];
             } else {
                 bf16* o = (bf16*)a.out + base;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) o[r] = f2bf(v[r]);
+                for (int r = 0; r < nr; ++r) o[r] = f2bf(v[r]);
             }
         }
     }
@@ -811,8 +810,9 @@ extern "C" {
 int t2s_unet_create(int K, int base, int levels, int max_batch, int H, int W, t2s_unet** out) {
     if (!out) return ufail(T2S_EINVAL, "out is NULL");
     *out = nullptr;
-    if (K < 1 || K > T2S_MAX_K || base < 4 || base % 4 || levels < 2 || levels > 6 || max_batch < 1)
-        return ufail(T2S_EINVAL, "K in [1, 8], base >= 4 (multiple of 4), levels in [2, 6], max_batch >= 1");
+    // every inner channel count must be a multiple of the 16-wide GEMM step
+    if (K < 1 || K > T2S_MAX_K || base < 16 || base % 16 || levels < 2 || levels > 6 || max_batch < 1)
+        return ufail(T2S_EINVAL, "K in [1, 8], base a positive multiple of 16, levels in [2, 6], max_batch >= 1");
     if (H % (1 << (levels - 1)) || W % (1 << (levels - 1)) || H < 2 || W < 2)
         return ufail(T2S_ESHAPE, "H and W must be divisible by 2^(levels-1)");
     t2s_unet* u = new t2s_unet();

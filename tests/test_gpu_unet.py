@@ -40,7 +40,7 @@ def test_mfma_lane_layout():
     assert np.array_equal(D, (A.astype(np.float64) @ B).astype(np.float32))
 
 
-def _tiny(seed, K=2, base=8, levels=3, H=16, W=16, B=2):
+def _tiny(seed, K=2, base=16, levels=3, H=16, W=16, B=2):
     rng = np.random.default_rng(seed)
     params = U.init_params(2 * K, base, levels, seed=seed, final_scale=1.0)
     params = params + 0.02 * rng.standard_normal(params.size).astype(np.float32)
@@ -55,7 +55,7 @@ def cos(a, b):
 
 def test_forward_matches_oracle():
     import torch
-    K, base, levels, H, W, B = 2, 8, 3, 16, 16, 2
+    K, base, levels, H, W, B = 2, 16, 3, 16, 16, 2
     params, _, _ = _tiny(1, K, base, levels, H, W, B)
     rng = np.random.default_rng(3)
     b0 = (rng.standard_normal((B, K, H, W)) + 1j * rng.standard_normal((B, K, H, W))).astype(np.complex64)
@@ -80,7 +80,7 @@ def test_forward_matches_oracle():
 
 
 def test_gradient_matches_oracle():
-    K, base, levels, H, W, B = 2, 8, 3, 16, 16, 2
+    K, base, levels, H, W, B = 2, 16, 3, 16, 16, 2
     params, x, t = _tiny(2, K, base, levels, H, W, B)
     net = T.UNet(K, base, levels, max_batch=B, H=H, W=W)
     net.set_params(params)
@@ -108,7 +108,7 @@ def test_gradient_matches_oracle():
 
 def test_training_reduces_loss():
     import torch
-    K, base, levels, H, W, B = 2, 8, 3, 32, 32, 4
+    K, base, levels, H, W, B = 2, 16, 3, 32, 32, 4
     rng = np.random.default_rng(5)
     params = U.init_params(2 * K, base, levels, seed=5)
     net = T.UNet(K, base, levels, max_batch=B, H=H, W=W)
