@@ -1,0 +1,228 @@
+"""Learned warm start for the slice solver: training pairs from the solver itself,
+U-Net training on the GPU, and the equal-residual comparison of ADMM started cold,
+from b0 = A^H y, and from the network's prediction.
+
+Every numerical step runs in libt2s.so (solver and network kernels); this module
+only moves data between the C entry points (PyTorch owns device memory).
+
+    python -m paper_1809_04195_amd.warmstart --out gpurun_out/warmstart.json
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import (T2S_ADJOINT, T2S_ALPHA, T2S_BATCHED, T2S_BATCHED_GRAPH, Plan, UNet, t2s_autotune)
+
+
+def log(msg):
+    print(f"[warmstart] {msg}", flush=True)
+
+
+# ---------------------------------------------------------------------------
+# training pairs: (b0, alpha after the fixed 100 x 5 schedule) per slice
+# ---------------------------------------------------------------------------
+
+
+def solve_chunk(phi, masks, sens, ksp, ptot, mid, cfg, seed):
+    """Reconstruct one chunk of training slices (one shape class per mask set).
+    Returns device tensors (b0, alpha) [n, K, ny, nz] in chunk order."""
+    import torch
+    n = sens.shape[0]
+    sets = sorted(set(int(m) for m in mid))
+    groups = [np.flatnonzero(mid == m) for m in sets]
+    ny, nz = masks.shape[2], masks.shape[3]
+    classes = [dict(ny=ny, nz=nz, ncoils=sens.shape[1], nslices=len(g), masks=masks[m]) for m, g in zip(sets, groups)]
+    plan = Plan(phi, classes, lam=cfg["lam"], rho=cfg["rho"], block=cfg["block"], n_outer=cfg["n_outer"],
+                n_cg=cfg["n_cg"], seed=seed)
+    for ci, g in enumerate(groups):
+        P = int(ptot[g[0]])
+        plan.load(ci, 0, np.ascontiguousarray(sens[g]), np.ascontiguousarray(ksp[g][:, :, :P]))
+    plan.reconstruct(T2S_BATCHED_GRAPH)
+    K = phi.shape[1]
+    b0 = torch.empty((n, K, ny, nz), dtype=torch.complex64, device="cuda")
+    alpha = torch.empty_like(b0)
+    for ci, g in enumerate(groups):
+        gi = torch.from_numpy(g).cuda()
+        b0[gi] = plan.read(ci, 0, len(g), T2S_ADJOINT, device=True)
+        alpha[gi] = plan.read(ci, 0, len(g), T2S_ALPHA, device=True)
+    torch.cuda.synchronize()
+    plan.close()
+    return b0, alpha
+
+
+def training_pairs(n, seed, mask_sets, phi, cfg, chunk=800, C=8):
+    import torch
+    from synth import make_training_chunk, training_masks
+
+    t0 = time.perf_counter()
+    masks = training_masks(seed, mask_sets, 256, 256, phi.shape[0], cfg["frac"])
+    log(f"{mask_sets} mask sets in {time.perf_counter() - t0:.1f} s")
+    b0s, als = [], []
+    for first in range(0, n, chunk):
+        m = min(chunk, n - first)
+        t1 = time.perf_counter()
+        sens, ksp, ptot, mid = make_training_chunk(first, m, seed, masks, C=C)
+        t2 = time.perf_counter()
+        b0, al = solve_chunk(phi, masks, sens, ksp, ptot, mid, cfg, seed + first)
+        b0s.append(b0)
+        als.append(al)
+        log(f"training slices {first}..{first + m - 1}: synthesised {t2 - t1:.1f} s, solved {time.perf_counter() - t2:.1f} s")
+        del sens, ksp
+    return torch.cat(b0s), torch.cat(als)
+
+
+# ---------------------------------------------------------------------------
+# training
+# ---------------------------------------------------------------------------
+
+
+def train(net, b0, alpha, epochs, batch, lr, seed):
+    import torch
+    n = b0.shape[0]
+    rng = np.random.default_rng(seed)
+    hist = []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        lr_ep = lr * (0.5 * (1 + np.cos(np.pi * ep / epochs)))      # cosine decay
+        losses = []
+        for i in range(0, n - batch + 1, batch):
+            idx = torch.from_numpy(perm[i:i + batch]).cuda()
+            xb = b0[idx].contiguous()
+            tb = alpha[idx].contiguous()
+            want = (i // batch) % 25 == 0
+            l = net.train_step(xb, tb, lr_ep, want_loss=want)
+            if want:
+                losses.append(l)
+        torch.cuda.synchronize()
+        hist.append(float(np.mean(losses)))
+        log(f"epoch {ep + 1}/{epochs}: mean sampled loss {hist[-1]:.5f} (lr {lr_ep:.2e}) at {time.perf_counter() - t0:.1f} s")
+    return hist, time.perf_counter() - t0
+
+
+# ---------------------------------------------------------------------------
+# equal-residual comparison
+# ---------------------------------------------------------------------------
+
+
+def run_tolerance(phi, cl, cfg, start, net=None, batch=16):
+    """Load, optionally warm start, reconstruct to tol.  start: 'cold' | 'b0' | 'net'."""
+    import torch
+    S = cl.nslices
+    plan = Plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=S, masks=cl.masks)], lam=cfg["lam"],
+                rho=cfg["rho"], block=cfg["block"], n_outer=cfg["n_outer"], n_cg=cfg["n_cg"], tol=cfg["tol"],
+                seed=cfg["seed"], freeze_window=5, freeze_stall=0.05, check_every=5)
+    dsens = torch.from_numpy(np.ascontiguousarray(cl.sens)).cuda()
+    dksp = torch.from_numpy(np.ascontiguousarray(cl.ksp)).cuda()
+    plan.load(0, 0, dsens, dksp)
+    t2s_autotune(plan.handle, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.load(0, 0, dsens, dksp)
+    a0 = None
+    if start != "cold":
+        b0 = plan.read(0, 0, S, T2S_ADJOINT, device=True)
+        if start == "b0":
+            a0 = b0
+        else:
+            a0 = torch.empty_like(b0)
+            for i in range(0, S, batch):
+                net.forward(b0[i:i + batch], a0[i:i + batch])
+        plan.set_initial(0, 0, a0)
+    code = plan.reconstruct(T2S_BATCHED_GRAPH)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    reps = [plan.report(0, s) for s in range(S)]
+    alpha = plan.read(0, 0, S, T2S_ALPHA, device=True)
+    plan.close()
+    its = np.array([r["outer_iterations"] for r in reps])
+    res = dict(start=start, s_per_volume=wall, slices_per_s=S / wall, outer_mean=float(its.mean()),
+               outer_max=int(its.max()), outer_min=int(its.min()),
+               converged=int(sum(r["converged"] for r in reps)), slices=S, code=int(code),
+               final_residual_max=float(max(max(r["r_primal"], r["r_dual"]) for r in reps)))
+    return res, alpha, a0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-slices", type=int, default=4000)
+    ap.add_argument("--mask-sets", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--train-seed", type=int, default=10)
+    ap.add_argument("--eval-slices", type=int, default=320)
+    ap.add_argument("--out", type=str, default="gpurun_out/warmstart.json")
+    ap.add_argument("--save-params", type=str, default="gpurun_out/unet_params.npy")
+    ap.add_argument("--save-samples", type=int, default=2, help="eval slices whose outputs are saved for oracle checks")
+    args = ap.parse_args()
+
+    import torch
+
+    from oracle import unet as U
+    from synth import CONFIGS, basis, make_config
+
+    assert torch.cuda.is_available()
+    cfg1 = dict(CONFIGS[1])
+    cfg3 = dict(CONFIGS[3])
+    phi = basis(cfg1["T"], cfg1["K"])
+    K = phi.shape[1]
+    out = dict(config=dict(train_slices=args.train_slices, mask_sets=args.mask_sets, epochs=args.epochs,
+                           batch=args.batch, lr=args.lr, eval_slices=args.eval_slices, tol=cfg3["tol"]))
+    t0 = time.perf_counter()
+    b0, alpha = training_pairs(args.train_slices, args.train_seed, args.mask_sets, phi, cfg1)
+    out["pairs_s"] = time.perf_counter() - t0
+    log(f"{args.train_slices} training pairs in {out['pairs_s']:.1f} s")
+
+    net = UNet(K, 32, 4, max_batch=args.batch, H=256, W=256)
+    net.set_params(U.init_params(2 * K, 32, 4, seed=args.train_seed))
+    hist, ttrain = train(net, b0, alpha, args.epochs, args.batch, args.lr, args.train_seed)
+    out["train"] = dict(loss_per_epoch=hist, seconds=ttrain,
+                        slices_per_s=args.train_slices * args.epochs / ttrain)
+    params = net.get_params()
+    if args.save_params:
+        os.makedirs(os.path.dirname(args.save_params) or ".", exist_ok=True)
+        np.save(args.save_params, params)
+    del b0, alpha
+    torch.cuda.empty_cache()
+
+    # held-out evaluation volume
+    d = make_config(3, max_slices=args.eval_slices)
+    cl = d["classes"][0]
+    runs = {}
+    sols = {}
+    for start in ("cold", "b0", "net"):
+        r, a, a0 = run_tolerance(phi, cl, cfg3, start, net)
+        runs[start] = r
+        sols[start] = (a, a0)
+        log(f"{start}: {r}")
+    ref = sols["cold"][0]
+    a0n = sols["net"][1]
+    a0b = sols["b0"][1]
+
+    def rel(x, y):
+        return float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
+
+    out["eval"] = runs
+    out["start_error_vs_solution"] = dict(net=rel(a0n, ref), b0=rel(a0b, ref), zero=1.0)
+    out["speedup_net_vs_cold"] = runs["cold"]["s_per_volume"] / runs["net"]["s_per_volume"]
+    out["speedup_b0_vs_cold"] = runs["cold"]["s_per_volume"] / runs["b0"]["s_per_volume"]
+    out["outer_saved_net_vs_cold"] = runs["cold"]["outer_mean"] - runs["net"]["outer_mean"]
+    if args.save_samples:
+        sel = np.linspace(0, cl.nslices - 1, args.save_samples + 2).round().astype(int)[1:-1]
+        np.savez(os.path.splitext(args.out)[0] + "_samples.npz", slices=sel,
+                 index=cl.slice_index[sel], net=a0n[sel].cpu().numpy(), solution=ref[sel].cpu().numpy())
+    json.dump(out, open(args.out, "w"), indent=1)
+    log(json.dumps(out))
+    net.close()
+
+
+if __name__ == "__main__":
+    main()

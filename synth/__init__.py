@@ -12,6 +12,8 @@ from .generate import (  # noqa: F401
     SliceSet,
     basis,
     make_config,
+    make_training_chunk,
     make_training_slices,
+    training_masks,
     vd_poisson_masks,
 )

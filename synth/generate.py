@@ -408,6 +408,63 @@ def make_config(cfg_id: int, slices=None, max_slices=None, workers=None):
     return dict(cfg=cfg, phi=phi, classes=classes)
 
 
+def _mask_job(args):
+    seed, T, ny, nz, frac = args
+    return vd_poisson_masks(seed, T, ny, nz, frac, 0.10)
+
+
+def training_masks(seed, mask_sets=40, ny=256, nz=256, T=80, frac=0.015, workers=None):
+    """The mask sets of the training workload (set m drawn with seed `seed * 1000 + m`)."""
+    workers = workers or min(16, os.cpu_count() or 1)
+    jobs = [(seed * 1000 + m, T, ny, nz, frac) for m in range(mask_sets)]
+    if workers > 1 and mask_sets > 1:
+        with mp.get_context("fork").Pool(min(workers, mask_sets)) as pool:
+            return np.stack(pool.map(_mask_job, jobs))
+    return np.stack([_mask_job(j) for j in jobs])
+
+
+def _train_job(i):
+    j = _JOB
+    g = j["first"] + i
+    rng = np.random.default_rng([j["seed"], 3, g])
+    ells = draw_ellipses(rng)
+    lab = labels_2d(ells, j["ny"], j["nz"])
+    s2 = coils_2d(j["C"], j["ny"], j["nz"], rot=rng.uniform(0, 2 * np.pi))
+    m = g % j["mask_sets"]
+    pd = np.array([e["pd"] for e in ells])
+    t2 = np.array([e["t2"] for e in ells])
+    j["sens"][i] = s2
+    y = acquire(lab, pd, t2, s2, j["masks"][m], rng.uniform(*j["snr_range"]), rng, locs=j["locs"][m])
+    j["ksp"][i, :, :y.shape[1]] = y
+    return i
+
+
+def make_training_chunk(first, n, seed, masks, C=8, snr_range=(15.0, 40.0), workers=None):
+    """Training slices [first, first + n): independent 2D phantoms (slice g uses mask set
+    g mod len(masks), coil ring rotated at random, SNR ~ U(snr_range)).  Returns
+    (sens [n, C, ny, nz], ksp [n, C, Pmax] zero padded, ptot [n], mask_id [n])."""
+    mask_sets, T, ny, nz = masks.shape
+    locs = [sample_locations(masks[m]) for m in range(mask_sets)]
+    ptot = np.array([locs[(first + i) % mask_sets][0].size for i in range(n)])
+    pmax = int(max(l[0].size for l in locs))
+    workers = max(1, min(workers or min(16, os.cpu_count() or 1), n // 4))
+    alloc = _shared_empty if workers > 1 else np.zeros
+    sens = alloc((n, C, ny, nz), np.complex64)
+    ksp = alloc((n, C, pmax), np.complex64)
+    _JOB.clear()
+    _JOB.update(first=first, seed=seed, ny=ny, nz=nz, C=C, mask_sets=mask_sets, masks=masks, locs=locs,
+                snr_range=snr_range, sens=sens, ksp=ksp)
+    if workers > 1:
+        with mp.get_context("fork").Pool(workers) as pool:
+            for _ in pool.imap_unordered(_train_job, range(n), chunksize=4):
+                pass
+    else:
+        for i in range(n):
+            _train_job(i)
+    _JOB.clear()
+    return sens, ksp, ptot, (first + np.arange(n)) % mask_sets
+
+
 def make_training_slices(n, seed, mask_sets=40, ny=256, nz=256, C=8, T=80, K=4, frac=0.015,
                          snr_range=(15.0, 40.0), first=0):
     """Independent 2D training slices (random phantom, coil rotation, SNR); slice i uses
