@@ -102,7 +102,8 @@ typedef struct t2s_slice_report {
     int k_freeze;          /* outer index whose shift was frozen (-1: never)         */
     int converged;         /* tolerance mode: 1 if max(r_p, r_d) <= tol             */
     double r_primal;       /* ||alpha - z|| / max(||alpha||, ||z||) after the last outer */
-    double r_dual;         /* rho ||z - z_prev|| / ||rho u|| (inf while u = 0)       */
+    double r_dual;         /* ||z - z_prev|| / max(||alpha||, ||z||) (dual residual   */
+                           /* rho (z - z_prev) relative to rho times the solution scale) */
 } t2s_slice_report;
 
 typedef struct t2s_plan t2s_plan;

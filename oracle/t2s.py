@@ -283,13 +283,14 @@ class AdmmResult:
 
 
 def admm_residuals(alpha, z, z_prev, u, rho):
-    """Relative primal residual ||alpha - z|| / max(||alpha||, ||z||) and dual
-    residual rho ||z - z_prev|| / ||rho u|| (+inf while u = 0)."""
+    """Primal residual alpha - z and dual residual rho (z - z_prev) (Boyd et al.,
+    Sec. 3.3), both relative to the scale of the solution:
+    r_p = ||alpha - z|| / max(||alpha||, ||z||),
+    r_d = rho ||z - z_prev|| / (rho max(||alpha||, ||z||)).   (0 when alpha = z = 0)"""
     na, nz = np.linalg.norm(alpha), np.linalg.norm(z)
     den = max(na, nz)
     rp = np.linalg.norm(alpha - z) / den if den > 0 else 0.0
-    nu = np.linalg.norm(rho * u)
-    rd = rho * np.linalg.norm(z - z_prev) / nu if nu > 0 else np.inf
+    rd = np.linalg.norm(z - z_prev) / den if den > 0 else 0.0
     return rp, rd
 
 

@@ -374,12 +374,14 @@ int ensure_graph(t2s_plan* plan, int mode) {
     return 0;
 }
 
+// relative primal / dual residuals from the per-outer sums (alpha - z, z - z_prev,
+// alpha, z, u, r squared norms): both relative to max(||alpha||, ||z||)
 void residuals_from_hist(const double* h, double rho, double* rp, double* rd) {
+    (void)rho;
     const double na = std::sqrt(h[2]), nzz = std::sqrt(h[3]);
     const double den = std::max(na, nzz);
     *rp = den > 0 ? std::sqrt(h[0]) / den : 0.0;
-    const double nu = rho * std::sqrt(h[4]);
-    *rd = nu > 0 ? rho * std::sqrt(h[1]) / nu : std::numeric_limits<double>::infinity();
+    *rd = den > 0 ? std::sqrt(h[1]) / den : 0.0;
 }
 
 }  // namespace
