@@ -43,7 +43,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct ClassPlan {
     int ny = 0, nz = 0, C = 0, S = 0, P = 0, gbase = 0;
     int npw = 0, nrr = 0, nllr = 0;
-    std::vector<float> psi;                 // [K(K+1)/2][nz][ny]
+    std::vector<float> psi;                 // [K(K+1)/2][nz][ny] (host copy, documented layout)
+    std::vector<float> psi_dev;             // pass-B order (see kernels.hpp)
     std::vector<int> row_ptr, ent_t, ent_p;
     std::vector<float> twy, twz;            // interleaved (re, im)
     size_t o_psi = 0, o_twy = 0, o_twz = 0, o_phi = 0, o_rowptr = 0, o_entt = 0, o_entp = 0;
@@ -477,6 +478,20 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.P = P;
         c.psi.resize((size_t)kk2 * N);
         for (size_t i = 0; i < c.psi.size(); ++i) c.psi[i] = (float)(acc[i] / (double)N);
+        {
+            int R1 = 0, R2 = 0;
+            t2s::reg_plan(ny, &R1, &R2);
+            const int KP = (kk2 + 3) / 4 * 4;
+            c.psi_dev.assign((size_t)nz * ny * KP, 0.f);
+            for (int zq = 0; zq < nz; ++zq)
+                for (int t = 0; t < R1; ++t)
+                    for (int k2 = 0; k2 < R2; ++k2) {
+                        const int yq = t + R1 * k2;
+                        for (int tri = 0; tri < kk2; ++tri)
+                            c.psi_dev[((((size_t)zq * R2 + k2) * (KP / 4) + tri / 4) * R1 + t) * 4 + tri % 4] =
+                                c.psi[(size_t)tri * N + (size_t)zq * ny + yq];
+                    }
+        }
         c.row_ptr.assign(N + 1, 0);
         for (int q = 0; q < N; ++q) c.row_ptr[q + 1] = c.row_ptr[q] + cnt[q + 1];
         c.ent_t.assign(std::max(P, 1), 0);
@@ -514,7 +529,7 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
     };
     for (ClassPlan& c : plan->cls) {
         const size_t N = (size_t)c.ny * c.nz;
-        c.o_psi = take(c.psi.size() * 4);
+        c.o_psi = take(c.psi_dev.size() * 4);
         c.o_twy = take((size_t)c.ny * 8);
         c.o_twz = take((size_t)c.nz * 8);
         c.o_phi = take((size_t)T * K * 4);
@@ -604,7 +619,7 @@ int t2s_plan_bind_workspace(t2s_plan* plan, void* dev, size_t bytes, void* strea
     for (ClassPlan& c : plan->cls) {
         fill_args(plan, c);
         char* b = plan->ws;
-        HIP_TRY(hipMemcpyAsync(b + c.o_psi, c.psi.data(), c.psi.size() * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(b + c.o_psi, c.psi_dev.data(), c.psi_dev.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(b + c.o_twy, c.twy.data(), c.twy.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(b + c.o_twz, c.twz.data(), c.twz.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(b + c.o_phi, plan->phi.data(), plan->phi.size() * 4, hipMemcpyHostToDevice, st));

@@ -184,12 +184,22 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
     float2* xw = xb + w * TB;
 
     float2 F[K][R2];
+    float2 nxt[R1];   // next coefficient's column, loaded while the current one is transformed
+    if (t < R2) {
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) nxt[n1] = colok ? col[R2 * n1 + t] : make_float2(0.f, 0.f);
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (t < R2) {
             float2 v[R1];
 #pragma unroll
-            for (int n1 = 0; n1 < R1; ++n1) v[n1] = colok ? col[(size_t)k * N + R2 * n1 + t] : make_float2(0.f, 0.f);
+            for (int n1 = 0; n1 < R1; ++n1) v[n1] = nxt[n1];
+            if (k + 1 < K) {
+#pragma unroll
+                for (int n1 = 0; n1 < R1; ++n1)
+                    nxt[n1] = colok ? col[(size_t)(k + 1) * N + R2 * n1 + t] : make_float2(0.f, 0.f);
+            }
             dft_dir<R1, false>(v);
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) xw[k1 * (R2 + 1) + t] = tw_mul<false>(v[k1], tw, t * k1);
@@ -206,10 +216,22 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
         __syncthreads();
     }
     if (t < R1 && colok) {
-        const float* psi = a.psi + (size_t)z * L + t;
+        // kernel table in pass-B order: float4 groups of the KP (>= K(K+1)/2, multiple
+        // of 4) values of frequency t + R1 k2 of column z, thread index fastest
+        constexpr int KT = K * (K + 1) / 2;
+        constexpr int KP = (KT + 3) / 4 * 4;
+        const float4* psi = (const float4*)a.psi + (size_t)z * R2 * (KP / 4) * R1 + t;
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) {
-            const size_t off = (size_t)R1 * k2;
+            float q[KP];
+#pragma unroll
+            for (int j = 0; j < KP / 4; ++j) {
+                const float4 w = psi[(k2 * (KP / 4) + j) * R1];
+                q[4 * j] = w.x;
+                q[4 * j + 1] = w.y;
+                q[4 * j + 2] = w.z;
+                q[4 * j + 3] = w.w;
+            }
             float2 v[K];
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) v[kk] = F[kk][k2];
@@ -220,9 +242,8 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
                 for (int l = 0; l < K; ++l) {
                     const int lo = kk < l ? kk : l, hi = kk < l ? l : kk;
                     const int tri = lo * K - (lo * (lo - 1)) / 2 + (hi - lo);
-                    const float q = psi[(size_t)tri * N + off];
-                    acc.x += q * v[l].x;
-                    acc.y += q * v[l].y;
+                    acc.x += q[tri] * v[l].x;
+                    acc.y += q[tri] * v[l].y;
                 }
                 F[kk][k2] = acc;
             }
@@ -333,12 +354,24 @@ __global__ __launch_bounds__(rows_threads<L>()) void k_passC(ClassArgs a, int s0
     float2 acc[R1];
 #pragma unroll
     for (int i = 0; i < R1; ++i) acc[i] = make_float2(0.f, 0.f);
+    // spectra of the next coil are loaded while the current one is transformed
+    const float2* T0 = a.tmp + ((size_t)s * a.C * a.K + k) * N + y0 + r3;
+    const size_t cstride = (size_t)a.K * N;
+    float2 nb[R2];
+    if (on3) {
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) nb[k2] = T0[(size_t)(t3 + R1 * k2) * ny];
+    }
     for (int c = 0; c < a.C; ++c) {
         if (on3) {
-            const float2* in = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + y0 + r3;
             float2 b[R2];
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) b[k2] = in[(size_t)(t3 + R1 * k2) * ny];
+            for (int k2 = 0; k2 < R2; ++k2) b[k2] = nb[k2];
+            if (c + 1 < a.C) {
+                const float2* in = T0 + (size_t)(c + 1) * cstride;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) nb[k2] = in[(size_t)(t3 + R1 * k2) * ny];
+            }
             dft_dir<R2, true>(b);
 #pragma unroll
             for (int m1 = 0; m1 < R2; ++m1) xr3[m1 * (R1 + 1) + t3] = tw_mul<true>(b[m1], tw, t3 * m1);
@@ -713,6 +746,19 @@ __global__ void k_llr_finalize(ClassArgs a, int s0) {
 // ---------------------------------------------------------------------------
 
 bool fft_supported(int L) { return fft_length_supported(L); }
+
+bool reg_plan(int L, int* R1, int* R2) {
+    switch (L) {
+#define X(n)                          \
+    case n:                           \
+        *R1 = RegPlan<n>::R1;         \
+        *R2 = RegPlan<n>::R2;         \
+        return true;
+        X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+#undef X
+    }
+    return false;
+}
 
 template <int L>
 static size_t rows_lds() { return (L + kRowTile * RegGeom<L>::TB) * sizeof(float2) + 16 * sizeof(double); }

@@ -27,7 +27,9 @@ struct ClassArgs {
     int block;                   // LLR block edge
     float tau, rho;              // LLR threshold lambda / rho, ADMM penalty
     uint64_t seed;
-    const float* psi;            // [K(K+1)/2][nz][ny]: upper triangle, uncentred, / (ny nz)
+    const float* psi;            // upper triangle of Psi, uncentred, / (ny nz), in pass-B order:
+                                 // [nz][R2][KP/4][R1][4] for frequency y' = t + R1 k2 (t < R1,
+                                 // k2 < R2), KP = K(K+1)/2 rounded up to a multiple of 4
     const float2* twy;           // W_ny^m, m < ny
     const float2* twz;           // W_nz^m, m < nz
     const float* phi;            // [T][K]
@@ -80,6 +82,8 @@ hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, i
 hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, hipStream_t st);
 
 bool fft_supported(int L);
+// two-step register plan L = R1 * R2 of the passes (false if L has no plan)
+bool reg_plan(int L, int* R1, int* R2);
 size_t lds_bytes_passA(int nz);
 size_t lds_bytes_passB(int ny, int K);
 int passB_columns(int ny, int K);
