@@ -111,6 +111,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy before timing (HBM counter calibration under rocprof)")
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="processes for input synthesis (0: auto); use 1 under a profiler (no fork)")
+    ap.add_argument("--fast-data", action="store_true",
+                    help="random inputs of the workload's shapes (same masks) instead of the phantom; "
+                         "for counter runs only: the solver's memory traffic does not depend on values")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with rocprof-measured HBM bytes per launch of the dominant kernel")
     args = ap.parse_args()
@@ -123,13 +128,25 @@ def main():
     from synth import make_config
 
     t0 = time.perf_counter()
-    d = make_config(args.config)
+    if args.fast_data:
+        d = make_config(args.config, max_slices=1, workers=1)
+        rng = np.random.default_rng(0)
+        for ci, c in enumerate(d["classes"]):
+            n = d["cfg"]["classes"][ci]["nslices"]
+            P = c.ksp.shape[2]
+            c.sens = (rng.standard_normal((n, c.ncoils, c.ny, c.nz)).astype(np.float32) * (1 + 0j)).astype(np.complex64)
+            c.sens /= np.sqrt((np.abs(c.sens) ** 2).sum(1, keepdims=True)).astype(np.float32)
+            c.ksp = (rng.standard_normal((n, c.ncoils, P)) + 1j * rng.standard_normal((n, c.ncoils, P))).astype(np.complex64)
+            c.slice_index = np.arange(n)
+            log(f"class {ci}: random inputs for {n} slices")
+    else:
+        d = make_config(args.config, workers=args.gen_workers or None)
     cfg, phi = d["cfg"], d["phi"]
     classes = d["classes"]
     log(f"generated {cfg['name']} in {time.perf_counter() - t0:.1f} s")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.fast_data:
         nprocs = args.cpu_procs or min(16, os.cpu_count() or 1)
         cpu = cpu_baseline(classes[0], phi, cfg, nprocs, args.cpu_outer)
         log(f"cpu baseline: {cpu['value']:.4f} slices/s ({cpu['sample']})")
