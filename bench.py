@@ -104,7 +104,7 @@ def main():
     ap.add_argument("--config", type=int, default=1, help="workload id (1: 320 x 256^2 volume)")
     ap.add_argument("--mode", choices=["batched", "graph", "per_slice"], default="batched",
                     help="launch schedule; 'graph' replays a captured outer iteration (no per-kernel events)")
-    ap.add_argument("--schedule", type=str, default="auto",
+    ap.add_argument("--schedule", type=str, default="0,1",
                     help="'auto' (autotuner), or CHUNK,STREAMS applied to every shape class")
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(16, cores))")
     ap.add_argument("--cpu-outer", type=int, default=6, help="outer iterations of each oracle slice")
@@ -116,8 +116,10 @@ def main():
     ap.add_argument("--fast-data", action="store_true",
                     help="random inputs of the workload's shapes (same masks) instead of the phantom; "
                          "for counter runs only: the solver's memory traffic does not depend on values")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with rocprof-measured HBM bytes per launch of the dominant kernel")
+    ap.add_argument("--traffic", type=str,
+                    default=os.path.join(ROOT, "profiles", "hbm_traffic_vol320_256x256_c8_t80_k4.json"),
+                    help="rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled HBM bytes per launch); ignored when "
+                         "the kernel source or the workload differs from the one the counters were taken on")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -229,8 +231,14 @@ def main():
         kd = kern[dom]
         traffic = None
         if args.traffic and os.path.exists(args.traffic):
+            import hashlib
             tr = json.load(open(args.traffic))
-            traffic = tr.get(dom)
+            src = os.path.join(ROOT, "paper_1809_04195_amd", "csrc", "kernels.hip")
+            cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            same_sched = all(list(x) == [int(v) for v in tr.get("schedule", "0,1").split(",")] for x in scheds)
+            if tr.get("kernels_source_sha256_16") == cur and tr.get("workload") == cfg["name"] and same_sched:
+                t = tr["traffic"].get(dom)
+                traffic = None if t is None else int(t["bytes_per_launch"])
         roofline = dict(bound="hbm", kernel=dom, achieved=round(kd["achieved_gbs"], 1), peak=HBM_PEAK_GBS,
                         unit="GB/s", frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
                         avg_launch_ms=round(kd["avg_ms"], 4), alg_bytes_per_launch=int(kd["alg_bytes_per_launch"]))

@@ -18,7 +18,7 @@ import time
 
 import numpy as np
 
-from . import (T2S_ADJOINT, T2S_ALPHA, T2S_BATCHED, T2S_BATCHED_GRAPH, Plan, UNet, t2s_autotune)
+from . import (T2S_ADJOINT, T2S_ALPHA, T2S_BATCHED, T2S_BATCHED_GRAPH, T2S_PER_SLICE, Plan, UNet, t2s_autotune)
 
 
 def log(msg):
@@ -112,8 +112,9 @@ def train(net, b0, alpha, epochs, batch, lr, seed):
 # ---------------------------------------------------------------------------
 
 
-def run_tolerance(phi, cl, cfg, start, net=None, batch=16):
-    """Load, optionally warm start, reconstruct to tol.  start: 'cold' | 'b0' | 'net'."""
+def run_tolerance(phi, cl, cfg, start, net=None, batch=16, mode=T2S_BATCHED_GRAPH):
+    """Load, optionally warm start, reconstruct to tol.  start: 'cold' | 'b0' | 'net';
+    mode: T2S_BATCHED_GRAPH (batched) or T2S_PER_SLICE (one launch sequence per slice)."""
     import torch
     S = cl.nslices
     plan = Plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=S, masks=cl.masks)], lam=cfg["lam"],
@@ -136,14 +137,14 @@ def run_tolerance(phi, cl, cfg, start, net=None, batch=16):
             for i in range(0, S, batch):
                 net.forward(b0[i:i + batch], a0[i:i + batch])
         plan.set_initial(0, 0, a0)
-    code = plan.reconstruct(T2S_BATCHED_GRAPH)
+    code = plan.reconstruct(mode)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     reps = [plan.report(0, s) for s in range(S)]
     alpha = plan.read(0, 0, S, T2S_ALPHA, device=True)
     plan.close()
     its = np.array([r["outer_iterations"] for r in reps])
-    res = dict(start=start, s_per_volume=wall, slices_per_s=S / wall, outer_mean=float(its.mean()),
+    res = dict(start=start, mode="per_slice" if mode == T2S_PER_SLICE else "batched_graph", s_per_volume=wall, slices_per_s=S / wall, outer_mean=float(its.mean()),
                outer_max=int(its.max()), outer_min=int(its.min()),
                converged=int(sum(r["converged"] for r in reps)), slices=S, code=int(code),
                final_residual_max=float(max(max(r["r_primal"], r["r_dual"]) for r in reps)))
@@ -162,6 +163,8 @@ def main():
     ap.add_argument("--out", type=str, default="gpurun_out/warmstart.json")
     ap.add_argument("--save-params", type=str, default="gpurun_out/unet_params.npy")
     ap.add_argument("--save-samples", type=int, default=2, help="eval slices whose outputs are saved for oracle checks")
+    ap.add_argument("--params", type=str, default="", help="trained parameters (.npy): skip data generation and training")
+    ap.add_argument("--plain", action="store_true", help="also run the plain solver: per-slice launches, cold start")
     args = ap.parse_args()
 
     import torch
@@ -176,22 +179,25 @@ def main():
     K = phi.shape[1]
     out = dict(config=dict(train_slices=args.train_slices, mask_sets=args.mask_sets, epochs=args.epochs,
                            batch=args.batch, lr=args.lr, eval_slices=args.eval_slices, tol=cfg3["tol"]))
-    t0 = time.perf_counter()
-    b0, alpha = training_pairs(args.train_slices, args.train_seed, args.mask_sets, phi, cfg1)
-    out["pairs_s"] = time.perf_counter() - t0
-    log(f"{args.train_slices} training pairs in {out['pairs_s']:.1f} s")
-
     net = UNet(K, 32, 4, max_batch=args.batch, H=256, W=256)
-    net.set_params(U.init_params(2 * K, 32, 4, seed=args.train_seed))
-    hist, ttrain = train(net, b0, alpha, args.epochs, args.batch, args.lr, args.train_seed)
-    out["train"] = dict(loss_per_epoch=hist, seconds=ttrain,
-                        slices_per_s=args.train_slices * args.epochs / ttrain)
-    params = net.get_params()
-    if args.save_params:
-        os.makedirs(os.path.dirname(args.save_params) or ".", exist_ok=True)
-        np.save(args.save_params, params)
-    del b0, alpha
-    torch.cuda.empty_cache()
+    if args.params:
+        net.set_params(np.load(args.params))
+        out["train"] = dict(params=args.params)
+    else:
+        t0 = time.perf_counter()
+        b0, alpha = training_pairs(args.train_slices, args.train_seed, args.mask_sets, phi, cfg1)
+        out["pairs_s"] = time.perf_counter() - t0
+        log(f"{args.train_slices} training pairs in {out['pairs_s']:.1f} s")
+        net.set_params(U.init_params(2 * K, 32, 4, seed=args.train_seed))
+        hist, ttrain = train(net, b0, alpha, args.epochs, args.batch, args.lr, args.train_seed)
+        out["train"] = dict(loss_per_epoch=hist, seconds=ttrain,
+                            slices_per_s=args.train_slices * args.epochs / ttrain)
+        params = net.get_params()
+        if args.save_params:
+            os.makedirs(os.path.dirname(args.save_params) or ".", exist_ok=True)
+            np.save(args.save_params, params)
+        del b0, alpha
+        torch.cuda.empty_cache()
 
     # held-out evaluation volume
     d = make_config(3, max_slices=args.eval_slices)
@@ -212,6 +218,12 @@ def main():
 
     out["eval"] = runs
     out["start_error_vs_solution"] = dict(net=rel(a0n, ref), b0=rel(a0b, ref), zero=1.0)
+    if args.plain:
+        r, _, _ = run_tolerance(phi, cl, cfg3, "cold", None, mode=T2S_PER_SLICE)
+        runs["plain"] = r
+        log(f"plain (per-slice launches, cold): {r}")
+        out["speedup_batched_net_vs_plain"] = r["s_per_volume"] / runs["net"]["s_per_volume"]
+        out["speedup_batched_cold_vs_plain"] = r["s_per_volume"] / runs["cold"]["s_per_volume"]
     out["speedup_net_vs_cold"] = runs["cold"]["s_per_volume"] / runs["net"]["s_per_volume"]
     out["speedup_b0_vs_cold"] = runs["cold"]["s_per_volume"] / runs["b0"]["s_per_volume"]
     out["outer_saved_net_vs_cold"] = runs["cold"]["outer_mean"] - runs["net"]["outer_mean"]
