@@ -259,6 +259,11 @@ int t2s_unet_train_step(t2s_unet* net, const void* b0, const void* target, int B
  * targets t, both [B][H][W][2K] (already normalised).  Synchronous. */
 int t2s_unet_loss_grad(t2s_unet* net, const float* x, const float* t, int B, double* loss, float* grad,
                        void* stream);
+/* Initial parameters into host `params` (param_count floats): He-normal weights
+ * (standard deviation sqrt(2 / fan_in)) from a 64-bit Mersenne twister seeded with
+ * `seed`, zero biases, the final 1x1 layer scaled by 0.1. */
+int t2s_unet_init_params(const t2s_unet* net, uint64_t seed, float* params);
+
 /* One 16x16x16 bf16 matrix-core product D = A B (host fp32 row-major, rounded to bf16
  * on input) -- a check of the lane layout the convolution kernels assume. */
 int t2s_unet_mfma_probe(const float* A, const float* B, float* D);

@@ -136,6 +136,7 @@ _SIGS = {
     "t2s_unet_loss_grad": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                             ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
                             ctypes.c_void_p], ctypes.c_int),
+    "t2s_unet_init_params": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "t2s_unet_mfma_probe": ([ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "t2s_block_shift": ([ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -419,6 +420,12 @@ class UNet:
         if p.size != self.nparams:
             raise ValueError(f"expected {self.nparams} parameters, got {p.size}")
         _check(lib().t2s_unet_set_params(self.handle, _fptr(p), _stream(stream)))
+
+    def init_params(self, seed=0):
+        """Library-generated initial parameters (host float32, packed)."""
+        p = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().t2s_unet_init_params(self.handle, ctypes.c_uint64(seed), _fptr(p)))
+        return p
 
     def get_params(self, stream=None):
         p = np.empty(self.nparams, dtype=np.float32)

@@ -1048,6 +1048,24 @@ int t2s_unet_loss_grad(t2s_unet* u, const float* x, const float* t, int B, doubl
     return 0;
 }
 
+int t2s_unet_init_params(const t2s_unet* u, uint64_t seed, float* host) {
+    if (!u || !host) return ufail(T2S_EINVAL, "NULL argument");
+    // He-normal weights (std sqrt(2 / fan_in)), zero biases, final 1x1 layer scaled by
+    // 0.1 so the untrained network is close to the identity through its residual
+    std::mt19937_64 gen(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (size_t li = 0; li < u->L.size(); ++li) {
+        const Layer& Ly = u->L[li];
+        const int fan_in = Ly.up ? Ly.cin : Ly.KS * Ly.KS * Ly.cin;
+        double sd = std::sqrt(2.0 / fan_in);
+        if (li + 1 == u->L.size()) sd *= 0.1;
+        const size_t nw = (size_t)Ly.KS * Ly.KS * Ly.cout * Ly.cin;
+        for (size_t i = 0; i < nw; ++i) host[Ly.woff + i] = (float)(sd * nd(gen));
+        for (int i = 0; i < Ly.nbias; ++i) host[Ly.boff + i] = 0.f;
+    }
+    return 0;
+}
+
 int t2s_unet_mfma_probe(const float* A, const float* B, float* D) {
     if (!A || !B || !D) return ufail(T2S_EINVAL, "NULL argument");
     std::vector<bf16> a(256), b(256);

@@ -169,7 +169,6 @@ def main():
 
     import torch
 
-    from oracle import unet as U
     from synth import CONFIGS, basis, make_config
 
     assert torch.cuda.is_available()
@@ -188,7 +187,7 @@ def main():
         b0, alpha = training_pairs(args.train_slices, args.train_seed, args.mask_sets, phi, cfg1)
         out["pairs_s"] = time.perf_counter() - t0
         log(f"{args.train_slices} training pairs in {out['pairs_s']:.1f} s")
-        net.set_params(U.init_params(2 * K, 32, 4, seed=args.train_seed))
+        net.set_params(net.init_params(args.train_seed))
         hist, ttrain = train(net, b0, alpha, args.epochs, args.batch, args.lr, args.train_seed)
         out["train"] = dict(loss_per_epoch=hist, seconds=ttrain,
                             slices_per_s=args.train_slices * args.epochs / ttrain)

@@ -184,3 +184,24 @@ def test_unet_create_validation_and_sizes():
     assert L.t2s_unet_workspace_bytes(h, ctypes.byref(n)) == 0 and n.value > 0
     assert L.t2s_unet_bind_workspace(h, None, 0, None) == T.T2S_ENOMEM
     assert L.t2s_unet_destroy(h) == 0
+
+
+def test_unet_init_params_follow_packing():
+    from oracle import unet as U
+    L = T.lib()
+    h = ctypes.c_void_p()
+    assert L.t2s_unet_create(4, 32, 4, 1, 64, 64, ctypes.byref(h)) == 0
+    n = U.param_count(8, 32, 4)
+    p = np.empty(n, np.float32)
+    assert L.t2s_unet_init_params(h, ctypes.c_uint64(7), p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))) == 0
+    P = U.unpack(p.astype(np.float64), 8, 32, 4)
+    for name, kind, k, ci, co in U.layer_specs(8, 32, 4):
+        W, b = P[name]
+        assert np.all(b == 0)
+        fan_in = k * k * ci if kind == "conv" else ci
+        sd = np.sqrt(2.0 / fan_in) * (0.1 if name == "final" else 1.0)
+        assert abs(W.std() / sd - 1) < 0.15, name
+    q = np.empty(n, np.float32)
+    L.t2s_unet_init_params(h, ctypes.c_uint64(7), q.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    assert np.array_equal(p, q)
+    L.t2s_unet_destroy(h)
