@@ -46,10 +46,8 @@ def alg_bytes_per_slice(kind, ny, nz, C, K, n_cg):
         return (first + (n_cg - 1) * rest) / n_cg
     if kind == "pass_b":       # read + write the C K intermediate, read Psi (upper triangle, fp32)
         return c8 * 2 * C * K + 4.0 * N * K * (K + 1) / 2
-    if kind == "pass_c":       # read C K intermediate, S, p; write w
-        return c8 * (C * K + C + 2 * K)
-    if kind == "cg_update":    # read x, r, p, w; write x, r
-        return c8 * 6 * K
+    if kind == "pass_c":       # read C K intermediate, S, p, x, r; write x, r (CG update fused)
+        return c8 * (C * K + C + 5 * K)
     if kind == "llr_admm":     # read alpha, u, z, r; write z, u, r
         return c8 * 7 * K
     if kind == "load_adjoint":
@@ -212,8 +210,7 @@ def main():
     value = n_slices / (ms_per_step / 1000.0)
 
     # per kernel family: algorithmic bytes moved during the timed region / summed event time
-    counts = {"pass_a": cfg["n_cg"], "pass_b": cfg["n_cg"], "pass_c": cfg["n_cg"], "cg_update": cfg["n_cg"],
-              "llr_admm": 1}
+    counts = {"pass_a": cfg["n_cg"], "pass_b": cfg["n_cg"], "pass_c": cfg["n_cg"], "llr_admm": 1}
     kern = {}
     for name, (n, ms) in prof.items():
         if n == 0:
@@ -246,7 +243,7 @@ def main():
     per_outer = 0.0
     for c in classes:
         for name, mult in (("pass_a", cfg["n_cg"]), ("pass_b", cfg["n_cg"]), ("pass_c", cfg["n_cg"]),
-                           ("cg_update", cfg["n_cg"]), ("llr_admm", 1)):
+                           ("llr_admm", 1)):
             per_outer += mult * c.nslices * alg_bytes_per_slice(name, c.ny, c.nz, c.ncoils, phi.shape[1], cfg["n_cg"])
     tot_bytes = per_outer * cfg["n_outer"] * args.steps
     out = {

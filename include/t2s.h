@@ -203,11 +203,11 @@ int t2s_get_psi(const t2s_plan* plan, int cls, float* out);
 
 #define T2S_KERNEL_PASS_A 0    /* S p + row FFT (first loop of Alg. 1)             */
 #define T2S_KERNEL_PASS_B 1    /* column FFT, Psi mix, column IFFT (second loop)    */
-#define T2S_KERNEL_PASS_C 2    /* row IFFT, coil combine, + rho p (third loop)      */
-#define T2S_KERNEL_CG 3        /* CG vector update                                  */
-#define T2S_KERNEL_LLR 4       /* LLR z-step fused with the ADMM updates            */
-#define T2S_KERNEL_LOAD 5      /* projection + adjoint of load_slices               */
-#define T2S_KERNEL_COUNT 6
+#define T2S_KERNEL_PASS_C 2    /* row IFFT, coil combine, + rho p (third loop); in  */
+                               /* CG fused with the x, r update                     */
+#define T2S_KERNEL_LLR 3       /* LLR z-step fused with the ADMM updates            */
+#define T2S_KERNEL_LOAD 4      /* projection + adjoint of load_slices               */
+#define T2S_KERNEL_COUNT 5
 
 /* Enable (1) or disable (0) event timing of every launch; enabling clears the totals. */
 int t2s_profile_enable(t2s_plan* plan, int enable);

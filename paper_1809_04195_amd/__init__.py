@@ -40,10 +40,9 @@ T2S_ADJOINT = 3
 T2S_KERNEL_PASS_A = 0
 T2S_KERNEL_PASS_B = 1
 T2S_KERNEL_PASS_C = 2
-T2S_KERNEL_CG = 3
-T2S_KERNEL_LLR = 4
-T2S_KERNEL_LOAD = 5
-KERNEL_NAMES = ("pass_a", "pass_b", "pass_c", "cg_update", "llr_admm", "load_adjoint")
+T2S_KERNEL_LLR = 3
+T2S_KERNEL_LOAD = 4
+KERNEL_NAMES = ("pass_a", "pass_b", "pass_c", "llr_admm", "load_adjoint")
 
 
 class t2s_params(ctypes.Structure):

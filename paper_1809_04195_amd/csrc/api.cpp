@@ -42,13 +42,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct ClassPlan {
     int ny = 0, nz = 0, C = 0, S = 0, P = 0, gbase = 0;
-    int npw = 0, nrr = 0, nllr = 0;
+    int nrw = 0, npb = 0, nllr = 0;
     std::vector<float> psi;                 // [K(K+1)/2][nz][ny] (host copy, documented layout)
     std::vector<float> psi_dev;             // pass-B order (see kernels.hpp)
     std::vector<int> row_ptr, ent_t, ent_p;
     std::vector<float> twy, twz;            // interleaved (re, im)
     size_t o_psi = 0, o_twy = 0, o_twz = 0, o_phi = 0, o_rowptr = 0, o_entt = 0, o_entp = 0;
-    size_t o_sens = 0, o_ksp = 0, o_vec[7] = {}, o_tmp = 0, o_pw = 0, o_rr = 0, o_g0 = 0, o_llr = 0,
+    size_t o_sens = 0, o_ksp = 0, o_vec[7] = {}, o_tmp = 0, o_pa = 0, o_pb = 0, o_rr = 0, o_g0 = 0, o_llr = 0,
            o_hist = 0, o_state = 0;
     std::vector<int> loaded;
     std::vector<int> outer_run, k_freeze, converged;
@@ -130,8 +130,8 @@ void fill_args(t2s_plan* plan, ClassPlan& c) {
     a.K = plan->prm.K;
     a.T = plan->prm.T;
     a.P = c.P;
-    a.npw = c.npw;
-    a.nrr = c.nrr;
+    a.nrw = c.nrw;
+    a.npb = c.npb;
     a.nllr = c.nllr;
     a.gbase = c.gbase;
     a.hist_len = plan->hist_len;
@@ -156,7 +156,8 @@ void fill_args(t2s_plan* plan, ClassPlan& c) {
     a.z = (float2*)(b + c.o_vec[5]);
     a.u = (float2*)(b + c.o_vec[6]);
     a.tmp = (float2*)(b + c.o_tmp);
-    a.pw = (double*)(b + c.o_pw);
+    a.pa = (double*)(b + c.o_pa);
+    a.pb = (double*)(b + c.o_pb);
     a.rr = (double*)(b + c.o_rr);
     a.g0 = (double*)(b + c.o_g0);
     a.llr = (double*)(b + c.o_llr);
@@ -218,7 +219,7 @@ thread_local Profiler* g_prof = nullptr;   // profiler of the plan being driven
 #define TIMED(kind) TimedLaunch timed_##__LINE__(g_prof, kind, st)
 #define TIMED_ON(kind, stream) TimedLaunch timed_on_##__LINE__(g_prof, kind, stream)
 
-PartialSrc rr_src(const ClassArgs& a, int buf) { return PartialSrc{a.rr + (size_t)buf * a.nrr, 2 * a.nrr, a.nrr}; }
+PartialSrc rr_src(const ClassArgs& a, int buf) { return PartialSrc{a.rr + (size_t)buf * a.nrw, 2 * a.nrw, a.nrw}; }
 PartialSrc g0_src(const ClassArgs& a) { return PartialSrc{a.g0, a.nllr, a.nllr}; }
 
 #define HIP_CHECK_LAUNCH(expr)                                                                 \
@@ -234,11 +235,11 @@ int run_normal(const ClassArgs& a, int s0, int count, const float2* src, int src
     {
         TIMED(T2S_KERNEL_PASS_A);
         HIP_CHECK_LAUNCH(t2s::launch_passA(a, s0, count, src, src_s0, 1, PartialSrc{nullptr, 0, 0},
-                                           PartialSrc{nullptr, 0, 0}, st));
+                                           PartialSrc{nullptr, 0, 0}, 0, st));
     }
     {
         TIMED(T2S_KERNEL_PASS_B);
-        HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_passB(a, s0, count, 0, 0, st));
     }
     {
         TIMED(T2S_KERNEL_PASS_C);
@@ -247,14 +248,20 @@ int run_normal(const ClassArgs& a, int s0, int count, const float2* src, int src
     return 0;
 }
 
-// Passes A, B, C of CG step i for slices [s0, s0 + count): in one launch each, or in
-// chunks of `chunk` slices spread round-robin over `ns` library streams, so that the
-// pass intermediate of the slices in flight stays in the on-package cache between
-// the passes.  The caller's stream waits for every chunk before it continues.
-int run_passes(t2s_plan* plan, const ClassArgs& a, int s0, int count, int i, int chunk, int ns, hipStream_t st) {
+// CG step i for slices [s0, s0 + count) as passes A, B, C with the vector update
+// fused into pass C: in one launch each, or in chunks of `chunk` slices spread
+// round-robin over `ns` library streams, so that the pass intermediate of the slices
+// in flight can stay in the on-package cache between the passes.  The caller's
+// stream waits for every chunk before it continues.
+// <r, r> partials: g0 at the start of the outer iteration (LLR kernel), then
+// rr[(i + 1) % 2] after step i.  With `update` false (schedule timing) pass C writes
+// M p to w instead, and x, r and the partial sums stay untouched.
+int run_passes(t2s_plan* plan, const ClassArgs& a, int s0, int count, int i, int chunk, int ns, bool update,
+               hipStream_t st) {
     const PartialSrc none{nullptr, 0, 0};
     const PartialSrc gcA = (i == 0) ? none : rr_src(a, i % 2);
     const PartialSrc gpA = (i == 0) ? none : (i == 1 ? g0_src(a) : rr_src(a, (i - 1) % 2));
+    const PartialSrc gcC = (i == 0) ? g0_src(a) : rr_src(a, i % 2);
     if (chunk <= 0 || chunk >= count) {
         chunk = count;
         ns = 1;
@@ -271,15 +278,18 @@ int run_passes(t2s_plan* plan, const ClassArgs& a, int s0, int count, int i, int
         const int cn = std::min(chunk, s0 + count - c0);
         {
             TIMED_ON(T2S_KERNEL_PASS_A, sq);
-            HIP_CHECK_LAUNCH(t2s::launch_passA(a, c0, cn, a.r, 0, i == 0 ? 1 : 0, gcA, gpA, sq));
+            HIP_CHECK_LAUNCH(t2s::launch_passA(a, c0, cn, a.r, 0, i == 0 ? 1 : 0, gcA, gpA, update, sq));
         }
         {
             TIMED_ON(T2S_KERNEL_PASS_B, sq);
-            HIP_CHECK_LAUNCH(t2s::launch_passB(a, c0, cn, 0, sq));
+            HIP_CHECK_LAUNCH(t2s::launch_passB(a, c0, cn, 0, update, sq));
         }
         {
             TIMED_ON(T2S_KERNEL_PASS_C, sq);
-            HIP_CHECK_LAUNCH(t2s::launch_passC(a, c0, cn, 0, a.rho, a.w, 0, sq));
+            if (update)
+                HIP_CHECK_LAUNCH(t2s::launch_passC_cg(a, c0, cn, gcC, (i + 1) % 2, sq));
+            else
+                HIP_CHECK_LAUNCH(t2s::launch_passC(a, c0, cn, 0, a.rho, a.w, 0, sq));
         }
     }
     if (ns > 1) {
@@ -295,14 +305,8 @@ int run_passes(t2s_plan* plan, const ClassArgs& a, int s0, int count, int i, int
 // device-side slice state, so the same launch sequence serves every iteration)
 int run_outer(t2s_plan* plan, const ClassArgs& a, int s0, int count, int chunk, int ns, hipStream_t st) {
     const int ncg = plan->prm.n_cg;
-    for (int i = 0; i < ncg; ++i) {
-        if (int e = run_passes(plan, a, s0, count, i, chunk, ns, st)) return e;
-        const PartialSrc gcU = (i == 0) ? g0_src(a) : rr_src(a, i % 2);
-        {
-            TIMED(T2S_KERNEL_CG);
-            HIP_CHECK_LAUNCH(t2s::launch_cg_update(a, s0, count, gcU, (i + 1) % 2, st));
-        }
-    }
+    for (int i = 0; i < ncg; ++i)
+        if (int e = run_passes(plan, a, s0, count, i, chunk, ns, true, st)) return e;
     {
         TIMED(T2S_KERNEL_LLR);
         HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrAdmm, 0, nullptr, nullptr, a.tau, 0, 0, st));
@@ -389,7 +393,7 @@ void residuals_from_hist(const double* h, double rho, double* rp, double* rd) {
 
 extern "C" {
 
-int t2s_version(void) { return 100; }
+int t2s_version(void) { return 101; }
 
 const char* t2s_last_error(void) { return g_err.c_str(); }
 
@@ -509,9 +513,9 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
                 }
         roots(ny, c.twy);
         roots(nz, c.twz);
-        c.npw = (ny / t2s::kRowTile) * K;
-        const size_t kn = (size_t)K * N;
-        c.nrr = (int)std::min<size_t>(256, std::max<size_t>(1, (kn + 4095) / 4096));
+        c.nrw = (ny / t2s::kRowTile) * K;
+        const int wb = t2s::passB_columns(ny, K);
+        c.npb = ((nz + wb - 1) / wb) * c.C;
         const int strips = (ny / p->block) * ((nz + 63) / 64);
         c.nllr = (strips + 3) / 4;
         c.loaded.assign(c.S, 0);
@@ -540,8 +544,9 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.o_ksp = take((size_t)c.S * c.C * std::max(c.P, 1) * 8);
         for (int v = 0; v < 7; ++v) c.o_vec[v] = take(vec_bytes(c, K));
         c.o_tmp = take((size_t)c.S * c.C * K * N * 8);
-        c.o_pw = take((size_t)c.S * c.npw * 8);
-        c.o_rr = take((size_t)c.S * 2 * c.nrr * 8);
+        c.o_pa = take((size_t)c.S * c.nrw * 8);
+        c.o_pb = take((size_t)c.S * c.npb * 8);
+        c.o_rr = take((size_t)c.S * 2 * c.nrw * 8);
         c.o_g0 = take((size_t)c.S * c.nllr * 8);
         c.o_llr = take((size_t)c.S * c.nllr * 8 * 8);
         c.o_hist = take((size_t)c.S * plan->hist_len * 8 * 8);
@@ -661,7 +666,7 @@ int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* s
         g_prof = &plan->prof;
         TIMED(T2S_KERNEL_LOAD);
         HIP_CHECK_LAUNCH(t2s::launch_project(a, first, count, st));
-        HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, st));
+        HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, 0, st));
         HIP_CHECK_LAUNCH(t2s::launch_passC(a, first, count, 1, 0.0f, a.b0, 0, st));
         HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, nullptr, 0, st));
     }
@@ -848,10 +853,11 @@ int t2s_autotune(t2s_plan* plan, int reps, void* stream) {
         float best = 1e30f;
         std::pair<int, int> pick{0, 1};
         for (auto cand : cands) {
-            // one warm-up, then `reps` timed CG steps (passes only: the solver state is untouched)
+            // one warm-up, then `reps` timed CG steps (passes only, pass C writing M p to w:
+            // the solver state is untouched)
             for (int r = 0; r <= reps; ++r) {
                 if (r == 1) HIP_TRY(hipEventRecord(e0, st));
-                if (int e = run_passes(plan, c.args, 0, c.S, 0, cand.first, cand.second, st)) {
+                if (int e = run_passes(plan, c.args, 0, c.S, 0, cand.first, cand.second, false, st)) {
                     g_prof = saved;
                     return e;
                 }

@@ -12,8 +12,12 @@
 //           every column of all K coefficient images, the K x K real symmetric
 //           mix Psi(n) at every k-space location, ny-point inverse FFT.
 //   pass C  (third loop): per (slice, 16-row tile, k): inverse nz-point FFT of
-//           the rows of every coil, sum_c conj(S_c) (.), + rho p, and the partial
-//           <p, Mp> of the CG step.
+//           the rows of every coil, sum_c conj(S_c) (.), + rho p.  Inside CG the
+//           vector update is fused here: the step length needs <p, M p>, which is
+//           known before pass C starts, because F is unitary and so
+//           <p, A^H A p> = sum_c sum_n (F S_c p)(n)^H Psi(n) (F S_c p)(n) is summed in
+//           pass B (which holds both sides in registers) and ||p||^2 in pass A.
+//           w = M p therefore never goes to memory.
 // The centring of F and the 1/N of the unnormalised FFT pair are folded into the
 // kernel table (uncentred order, / N), so no phase-modulation pass exists.
 //
@@ -55,6 +59,23 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
+// sum over a workgroup of any size >= 64 whose last wave may be partial (lanes past
+// blockDim hold no data, so the cross-lane steps run only in the full first wave);
+// sh: blockDim doubles of LDS; fixed order; result valid in thread 0
+__device__ __forceinline__ double block_sum_ragged(double v, double* sh) {
+    const int tid = threadIdx.x, n = blockDim.x;
+    __syncthreads();
+    sh[tid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid < 64) {
+        for (int i = tid; i < n; i += 64) r += sh[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+    }
+    return r;
+}
+
 __device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[4 * s] != 0; }
 
 __host__ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
@@ -84,11 +105,14 @@ constexpr int rows_threads() { return kRowTile * RegGeom<L>::P; }
 // ---------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(rows_threads<L>()) void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
-                                                              int src_s0, int first, PartialSrc gc, PartialSrc gp) {
+                                                              int src_s0, int first, PartialSrc gc, PartialSrc gp,
+                                                              int want_pp) {
     using G = RegGeom<L>;
     constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
+    static_assert(NT % 64 == 0, "block_sum needs whole waves");
     __shared__ float2 tw[L];
     __shared__ float2 xb[RT * TB];
+    __shared__ double red[16];
 
     const int s = s0 + blockIdx.z;
     if (!slice_active(a, s)) return;
@@ -113,6 +137,7 @@ __global__ __launch_bounds__(rows_threads<L>()) void k_passA(ClassArgs a, int s0
     const float2* rs = src + ((size_t)(s - src_s0) * a.K + k) * N + rowoff;
     float2* ps = a.p + ((size_t)s * a.K + k) * N + rowoff;
     float2 pv[R1];
+    double pp = 0.0;
     if (on1) {
 #pragma unroll
         for (int n1 = 0; n1 < R1; ++n1) {
@@ -124,7 +149,12 @@ __global__ __launch_bounds__(rows_threads<L>()) void k_passA(ClassArgs a, int s0
             }
             ps[pos] = v;
             pv[n1] = v;
+            pp += (double)v.x * v.x + (double)v.y * v.y;
         }
+    }
+    if (want_pp) {
+        const double tot = block_sum(pp, red);
+        if (tid == 0) a.pa[(size_t)s * a.nrw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
     }
     __syncthreads();
     float2* xr1 = xb + r1 * TB;
@@ -163,9 +193,10 @@ template <int L>
 constexpr int colB() { return 256 / RegGeom<L>::P; }
 
 template <int L, int K>
-__global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a, int s0) {
+__global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a, int s0, int want_quad) {
     using G = RegGeom<L>;
     constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, W = colB<L>(), NT = W * P;
+    static_assert(NT >= 64, "block_sum_ragged needs a full first wave");
     __shared__ float2 tw[L];
     __shared__ float2 xb[W * TB];
 
@@ -215,6 +246,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
         }
         __syncthreads();
     }
+    double quad = 0.0;   // sum over this thread's frequencies of v^H Psi v
     if (t < R1 && colok) {
         // kernel table in pass-B order: float4 groups of the KP (>= K(K+1)/2, multiple
         // of 4) values of frequency t + R1 k2 of column z, thread index fastest
@@ -235,6 +267,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
             float2 v[K];
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) v[kk] = F[kk][k2];
+            float qf = 0.0f;
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 float2 acc = make_float2(0.f, 0.f);
@@ -246,7 +279,9 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
                     acc.y += q[tri] * v[l].y;
                 }
                 F[kk][k2] = acc;
+                qf += v[kk].x * acc.x + v[kk].y * acc.y;
             }
+            quad += (double)qf;
         }
     }
 #pragma unroll
@@ -271,6 +306,13 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
             }
         }
         __syncthreads();
+    }
+    if (want_quad) {
+        // W P threads need not fill whole waves (e.g. 12 x 20 for ny = 320); the
+        // exchange buffer is free after the last transform and holds the partials
+        static_assert(W * TB * sizeof(float2) >= NT * sizeof(double), "exchange buffer too small");
+        const double tot = block_sum_ragged(quad, reinterpret_cast<double*>(xb));
+        if (tid == 0) a.pb[(size_t)s * a.npb + c * gridDim.x + blockIdx.x] = tot;
     }
 }
 
@@ -322,13 +364,16 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
 // ---------------------------------------------------------------------------
 // pass C: per (row tile, k): for every coil, read the transposed spectra (row-
 // fastest lanes), inverse row FFT, conj(S_c) (.) accumulated in registers; then
-// w = acc + rho p and the partial <p, w> (MODE 0), or b0 = acc (MODE 1).
+// out = acc + rho_add p (MODE 0), out = acc (MODE 1), or the CG step (MODE 2):
+// w = acc + rho p, a = gamma / <p, M p>, x += a p, r -= a w, partial <r, r>.
 // ---------------------------------------------------------------------------
 template <int L, int MODE>
 __global__ __launch_bounds__(rows_threads<L>()) void k_passC(ClassArgs a, int s0, float rho_add,
-                                                              float2* __restrict__ outp, int out_s0) {
+                                                              float2* __restrict__ outp, int out_s0, PartialSrc gc,
+                                                              int out_buf) {
     using G = RegGeom<L>;
     constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
+    static_assert(NT % 64 == 0, "block_sum needs whole waves");
     __shared__ float2 tw[L];
     __shared__ float2 xb[RT * TB];
     __shared__ double red[16];
@@ -388,26 +433,50 @@ __global__ __launch_bounds__(rows_threads<L>()) void k_passC(ClassArgs a, int s0
         }
         __syncthreads();
     }
-    float2* out = outp + ((size_t)(s - out_s0) * a.K + k) * N + rowoff;
-    if constexpr (MODE == 0) {
-        const float2* pp = a.p + ((size_t)s * a.K + k) * N + rowoff;
+    if constexpr (MODE == 2) {
+        // <p, M p> = <p, A^H A p> (pass-B partials) + rho ||p||^2 (pass-A partials)
+        const double gamma = partial_sum(gc, s);
+        const double pmp = partial_sum(PartialSrc{a.pb, a.npb, a.npb}, s) +
+                           (double)a.rho * partial_sum(PartialSrc{a.pa, a.nrw, a.nrw}, s);
+        const float alpha = (gamma > 0.0 && pmp > 0.0) ? (float)(gamma / pmp) : 0.0f;
+        const size_t vo = ((size_t)s * a.K + k) * N + rowoff;
+        const float2* pp = a.p + vo;
+        float2* xx = a.x + vo;
+        float2* rr = a.r + vo;
+        const float rho = a.rho;
         double dot = 0.0;
         if (on1) {
 #pragma unroll
             for (int m2 = 0; m2 < R1; ++m2) {
                 const int pos = t1 + R2 * m2;
                 const float2 pv = pp[pos];
-                const float2 w = make_float2(acc[m2].x + rho_add * pv.x, acc[m2].y + rho_add * pv.y);
-                out[pos] = w;
-                dot += (double)pv.x * (double)w.x + (double)pv.y * (double)w.y;
+                float2 xv = xx[pos], rv = rr[pos];
+                const float2 w = make_float2(acc[m2].x + rho * pv.x, acc[m2].y + rho * pv.y);
+                xv.x += alpha * pv.x;
+                xv.y += alpha * pv.y;
+                rv.x -= alpha * w.x;
+                rv.y -= alpha * w.y;
+                xx[pos] = xv;
+                rr[pos] = rv;
+                dot += (double)rv.x * rv.x + (double)rv.y * rv.y;
             }
         }
         const double tot = block_sum(dot, red);
-        if (tid == 0) a.pw[(size_t)s * a.npw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
+        if (tid == 0) a.rr[((size_t)s * 2 + out_buf) * a.nrw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
     } else {
+        float2* out = outp + ((size_t)(s - out_s0) * a.K + k) * N + rowoff;
         if (on1) {
+            const float2* pp = a.p + ((size_t)s * a.K + k) * N + rowoff;
 #pragma unroll
-            for (int m2 = 0; m2 < R1; ++m2) out[t1 + R2 * m2] = acc[m2];
+            for (int m2 = 0; m2 < R1; ++m2) {
+                const int pos = t1 + R2 * m2;
+                float2 w = acc[m2];
+                if constexpr (MODE == 0) {
+                    const float2 pv = pp[pos];
+                    w = make_float2(w.x + rho_add * pv.x, w.y + rho_add * pv.y);
+                }
+                out[pos] = w;
+            }
         }
     }
 }
@@ -447,39 +516,6 @@ __global__ __launch_bounds__(kThreads) void k_project(ClassArgs a, int s0) {
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
         if (k < K) out[(size_t)k * N] = cscale(acc[k], sc);
-}
-
-// ---------------------------------------------------------------------------
-// CG update: a = gamma / Re<p, w>;  x += a p;  r -= a w;  partial <r, r>
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_cg_update(ClassArgs a, int s0, PartialSrc gc, int out_buf) {
-    __shared__ double red[kThreads / 64];
-    const int s = s0 + blockIdx.z;
-    if (!slice_active(a, s)) return;
-    const double gamma = partial_sum(gc, s);
-    PartialSrc pws{a.pw, a.npw, a.npw};
-    const double pw = partial_sum(pws, s);
-    const float alpha = (gamma > 0.0 && pw > 0.0) ? (float)(gamma / pw) : 0.0f;
-    const size_t n = (size_t)a.K * a.ny * a.nz;
-    const size_t base = (size_t)s * n;
-    float2* x = a.x + base;
-    float2* r = a.r + base;
-    const float2* p = a.p + base;
-    const float2* w = a.w + base;
-    double dot = 0.0;
-    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (size_t)gridDim.x * kThreads) {
-        const float2 pv = p[e], wv = w[e];
-        float2 xv = x[e], rv = r[e];
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        rv.x -= alpha * wv.x;
-        rv.y -= alpha * wv.y;
-        x[e] = xv;
-        r[e] = rv;
-        dot += (double)rv.x * rv.x + (double)rv.y * rv.y;
-    }
-    const double tot = block_sum(dot, red);
-    if (threadIdx.x == 0) a.rr[((size_t)s * 2 + out_buf) * a.nrr + blockIdx.x] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -795,12 +831,13 @@ int passB_columns(int ny, int) {
 }
 
 hipError_t launch_passA(const ClassArgs& a, int s0, int count, const float2* src, int src_s0, int first,
-                        PartialSrc gc, PartialSrc gp, hipStream_t st) {
+                        PartialSrc gc, PartialSrc gp, int want_pp, hipStream_t st) {
     const dim3 grid(a.ny / kRowTile, a.K, count);
     switch (a.nz) {
-#define X(L)                                                                                             \
-    case L:                                                                                              \
-        hipLaunchKernelGGL(k_passA<L>, grid, dim3(rows_threads<L>()), 0, st, a, s0, src, src_s0, first, gc, gp); \
+#define X(L)                                                                                                   \
+    case L:                                                                                                    \
+        hipLaunchKernelGGL(k_passA<L>, grid, dim3(rows_threads<L>()), 0, st, a, s0, src, src_s0, first, gc, gp, \
+                           want_pp);                                                                           \
         break;
         T2S_FOR_LENGTHS(X)
 #undef X
@@ -811,7 +848,7 @@ hipError_t launch_passA(const ClassArgs& a, int s0, int count, const float2* src
 }
 
 template <int L>
-static hipError_t launch_passB_L(const ClassArgs& a, int s0, int count, int mode, hipStream_t st) {
+static hipError_t launch_passB_L(const ClassArgs& a, int s0, int count, int mode, int wq, hipStream_t st) {
     constexpr int W = colB<L>();
     const dim3 grid((a.nz + W - 1) / W, a.C, count);
     const dim3 block(W * RegGeom<L>::P);
@@ -820,22 +857,22 @@ static hipError_t launch_passB_L(const ClassArgs& a, int s0, int count, int mode
         return hipGetLastError();
     }
     switch (a.K) {
-        case 1: hipLaunchKernelGGL((k_passB<L, 1>), grid, block, 0, st, a, s0); break;
-        case 2: hipLaunchKernelGGL((k_passB<L, 2>), grid, block, 0, st, a, s0); break;
-        case 3: hipLaunchKernelGGL((k_passB<L, 3>), grid, block, 0, st, a, s0); break;
-        case 4: hipLaunchKernelGGL((k_passB<L, 4>), grid, block, 0, st, a, s0); break;
-        case 5: hipLaunchKernelGGL((k_passB<L, 5>), grid, block, 0, st, a, s0); break;
-        case 6: hipLaunchKernelGGL((k_passB<L, 6>), grid, block, 0, st, a, s0); break;
-        case 7: hipLaunchKernelGGL((k_passB<L, 7>), grid, block, 0, st, a, s0); break;
-        case 8: hipLaunchKernelGGL((k_passB<L, 8>), grid, block, 0, st, a, s0); break;
+        case 1: hipLaunchKernelGGL((k_passB<L, 1>), grid, block, 0, st, a, s0, wq); break;
+        case 2: hipLaunchKernelGGL((k_passB<L, 2>), grid, block, 0, st, a, s0, wq); break;
+        case 3: hipLaunchKernelGGL((k_passB<L, 3>), grid, block, 0, st, a, s0, wq); break;
+        case 4: hipLaunchKernelGGL((k_passB<L, 4>), grid, block, 0, st, a, s0, wq); break;
+        case 5: hipLaunchKernelGGL((k_passB<L, 5>), grid, block, 0, st, a, s0, wq); break;
+        case 6: hipLaunchKernelGGL((k_passB<L, 6>), grid, block, 0, st, a, s0, wq); break;
+        case 7: hipLaunchKernelGGL((k_passB<L, 7>), grid, block, 0, st, a, s0, wq); break;
+        case 8: hipLaunchKernelGGL((k_passB<L, 8>), grid, block, 0, st, a, s0, wq); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, hipStream_t st) {
+hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, int want_quad, hipStream_t st) {
     switch (a.ny) {
-#define X(L) case L: return launch_passB_L<L>(a, s0, count, mode, st);
+#define X(L) case L: return launch_passB_L<L>(a, s0, count, mode, want_quad, st);
         T2S_FOR_LENGTHS(X)
 #undef X
         default:
@@ -846,13 +883,32 @@ hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, hipStre
 hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float rho_add, float2* out,
                         int out_s0, hipStream_t st) {
     const dim3 grid(a.ny / kRowTile, a.K, count);
+    const PartialSrc none{nullptr, 0, 0};
     switch (a.nz) {
-#define X(L)                                                                                               \
-    case L:                                                                                                \
-        if (mode == 0)                                                                                     \
-            hipLaunchKernelGGL((k_passC<L, 0>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0); \
-        else                                                                                               \
-            hipLaunchKernelGGL((k_passC<L, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0); \
+#define X(L)                                                                                                  \
+    case L:                                                                                                   \
+        if (mode == 0)                                                                                        \
+            hipLaunchKernelGGL((k_passC<L, 0>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0, \
+                               none, 0);                                                                      \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_passC<L, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0, \
+                               none, 0);                                                                      \
+        break;
+        T2S_FOR_LENGTHS(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_passC_cg(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st) {
+    const dim3 grid(a.ny / kRowTile, a.K, count);
+    switch (a.nz) {
+#define X(L)                                                                                                 \
+    case L:                                                                                                  \
+        hipLaunchKernelGGL((k_passC<L, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, 0.0f, nullptr, 0, gc, \
+                           out_buf);                                                                         \
         break;
         T2S_FOR_LENGTHS(X)
 #undef X
@@ -866,12 +922,6 @@ hipError_t launch_project(const ClassArgs& a, int s0, int count, hipStream_t st)
     const int N = a.ny * a.nz;
     const dim3 grid((N + kThreads - 1) / kThreads, a.C, count);
     hipLaunchKernelGGL(k_project, grid, dim3(kThreads), 0, st, a, s0);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_update(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st) {
-    const dim3 grid(a.nrr, 1, count);
-    hipLaunchKernelGGL(k_cg_update, grid, dim3(kThreads), 0, st, a, s0, gc, out_buf);
     return hipGetLastError();
 }
 

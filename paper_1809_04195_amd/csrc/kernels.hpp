@@ -21,7 +21,8 @@ struct PartialSrc {
 // Device view of one shape class (all slices of the class in one allocation).
 struct ClassArgs {
     int ny, nz, C, K, T, P;      // grid, coils, subspace, echoes, samples per coil
-    int npw, nrr, nllr;          // partial-sum counts per slice (pass C, CG update, LLR)
+    int nrw, npb, nllr;          // partial-sum counts per slice: row-pass workgroups (passes A
+                                 // and C: ny / kRowTile * K), pass-B workgroups, LLR workgroups
     int gbase;                   // global index of the class's slice 0
     int hist_len;                // outer-iteration capacity of the residual history
     int block;                   // LLR block edge
@@ -40,8 +41,9 @@ struct ClassArgs {
     float2* ksp;                 // [S][C][P]
     float2 *b0, *x, *r, *p, *w, *z, *u;   // [S][K][ny][nz]
     float2* tmp;                 // [S][C][K][nz][ny]  pass intermediate (k-space, transposed)
-    double* pw;                  // [S][npw]
-    double* rr;                  // [S][2][nrr]
+    double* pa;                  // [S][nrw]    ||p||^2 partials of pass A
+    double* pb;                  // [S][npb]    k-space partials of <p, A^H A p> (pass B)
+    double* rr;                  // [S][2][nrw] <r, r> partials of the CG update (pass C)
     double* g0;                  // [S][nllr]   <r, r> at the start of an outer iteration
     double* llr;                 // [S][nllr][8] residual partial sums of the z-step
     double* hist;                // [S][hist_len][8] per-outer residual sums
@@ -55,20 +57,24 @@ enum LlrMode { kLlrAdmm = 0, kLlrProx = 1 };
 // s0/count: slices [s0, s0 + count) of the class.
 
 // p = first ? src : r + beta p (beta from gc / gp); tmp[c][k] = FFT_z(S_c p_k), transposed
-// (src holds slices [src_s0, ...): slice s reads src + (s - src_s0) K N)
+// (src holds slices [src_s0, ...): slice s reads src + (s - src_s0) K N); with
+// want_pp the partial ||p||^2 of every workgroup goes to pa
 hipError_t launch_passA(const ClassArgs& a, int s0, int count, const float2* src, int src_s0, int first,
-                        PartialSrc gc, PartialSrc gp, hipStream_t st);
-// mode 0: column FFT, Psi mix, column IFFT (in place on tmp); mode 1: column IFFT only
-hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, hipStream_t st);
-// mode 0: out = sum_c conj(S_c) IFFT_z(tmp) + rho_add p, partial <p, out> into pw
+                        PartialSrc gc, PartialSrc gp, int want_pp, hipStream_t st);
+// mode 0: column FFT, Psi mix, column IFFT (in place on tmp), with want_quad the
+// partial k-space sums of <p, A^H A p> to pb; mode 1: column IFFT only
+hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, int want_quad, hipStream_t st);
+// mode 0: out = sum_c conj(S_c) IFFT_z(tmp) + rho_add p
 // mode 1: out = sum_c conj(S_c) IFFT_z(tmp)
 // (out holds slices [out_s0, ...))
 hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float rho_add, float2* out,
                         int out_s0, hipStream_t st);
+// CG step with the update fused: w = sum_c conj(S_c) IFFT_z(tmp) + rho p stays in
+// registers; a = gamma / (sum pb + rho sum pa) with gamma from gc; x += a p,
+// r -= a w; partial <r, r> into rr[out_buf]
+hipError_t launch_passC_cg(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st);
 // tmp[c][k] = projected, sign-modulated, uncentred k-space of the samples (adjoint input)
 hipError_t launch_project(const ClassArgs& a, int s0, int count, hipStream_t st);
-// x += a p, r -= a w with a = gamma / <p, w>; partial <r, r> into rr[out_buf]
-hipError_t launch_cg_update(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st);
 // x = z = alpha0 (or 0), u = 0, r = b0 - (sub_w ? w : 0); partial <r, r> into g0
 hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alpha0, int sub_w, hipStream_t st);
 // ADMM z/u/r update with the shift of the slice's outer counter (mode kLlrAdmm;

@@ -5,7 +5,9 @@ from b0 = A^H y, and from the network's prediction.
 Every numerical step runs in libt2s.so (solver and network kernels); this module
 only moves data between the C entry points (PyTorch owns device memory).
 
-    python -m paper_1809_04195_amd.warmstart --out gpurun_out/warmstart.json
+    python -m paper_1809_04195_amd.warmstart --workload eval320
+    python -m paper_1809_04195_amd.warmstart --workload vol512 --train-only
+    python -m paper_1809_04195_amd.warmstart --workload vol512 --params <saved .npy> --plain
 """
 
 from __future__ import annotations
@@ -57,13 +59,13 @@ def solve_chunk(phi, masks, sens, ksp, ptot, mid, cfg, seed):
     return b0, alpha
 
 
-def training_pairs(n, seed, mask_sets, phi, cfg, chunk=800, C=8):
+def training_pairs(n, seed, mask_sets, phi, cfg, ny=256, nz=256, C=8, chunk=800):
     import torch
     from synth import make_training_chunk, training_masks
 
     t0 = time.perf_counter()
-    masks = training_masks(seed, mask_sets, 256, 256, phi.shape[0], cfg["frac"])
-    log(f"{mask_sets} mask sets in {time.perf_counter() - t0:.1f} s")
+    masks = training_masks(seed, mask_sets, ny, nz, phi.shape[0], cfg["frac"])
+    log(f"{mask_sets} mask sets of {ny}x{nz} in {time.perf_counter() - t0:.1f} s")
     b0s, als = [], []
     for first in range(0, n, chunk):
         m = min(chunk, n - first)
@@ -151,40 +153,58 @@ def run_tolerance(phi, cl, cfg, start, net=None, batch=16, mode=T2S_BATCHED_GRAP
     return res, alpha, a0
 
 
+# Workloads: the training geometry (2D phantoms, its own masks) follows the volume
+# the network is evaluated on; targets are the fixed 100 x 5 schedule's solution.
+WORKLOADS = {
+    "eval320": dict(eval_cfg=3, ny=256, nz=256, C=8, frac=0.015, chunk=800),
+    "vol512": dict(eval_cfg=4, ny=384, nz=384, C=16, frac=0.01, chunk=200),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="eval320",
+                    help="eval320: held-out 320-slice 256^2 C8 K4 volume; vol512: 512-slice 384^2 C16 T100 K5 volume")
     ap.add_argument("--train-slices", type=int, default=4000)
     ap.add_argument("--mask-sets", type=int, default=40)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--train-seed", type=int, default=10)
-    ap.add_argument("--eval-slices", type=int, default=320)
-    ap.add_argument("--out", type=str, default="gpurun_out/warmstart.json")
-    ap.add_argument("--save-params", type=str, default="gpurun_out/unet_params.npy")
+    ap.add_argument("--eval-slices", type=int, default=0, help="0: the whole volume")
+    ap.add_argument("--out", type=str, default="")
+    ap.add_argument("--save-params", type=str, default="")
     ap.add_argument("--save-samples", type=int, default=2, help="eval slices whose outputs are saved for oracle checks")
     ap.add_argument("--params", type=str, default="", help="trained parameters (.npy): skip data generation and training")
+    ap.add_argument("--train-only", action="store_true", help="stop after training (parameters saved)")
     ap.add_argument("--plain", action="store_true", help="also run the plain solver: per-slice launches, cold start")
     args = ap.parse_args()
+    wl = WORKLOADS[args.workload]
+    args.out = args.out or f"gpurun_out/warmstart_{args.workload}.json"
+    args.save_params = args.save_params or f"gpurun_out/unet_params_{args.workload}.npy"
 
     import torch
 
     from synth import CONFIGS, basis, make_config
 
     assert torch.cuda.is_available()
-    cfg1 = dict(CONFIGS[1])
-    cfg3 = dict(CONFIGS[3])
-    phi = basis(cfg1["T"], cfg1["K"])
+    ecfg = dict(CONFIGS[wl["eval_cfg"]])
+    tcfg = dict(ecfg, n_outer=100, n_cg=5, tol=0.0, frac=wl["frac"])      # schedule of the training targets
+    phi = basis(ecfg["T"], ecfg["K"])
     K = phi.shape[1]
-    out = dict(config=dict(train_slices=args.train_slices, mask_sets=args.mask_sets, epochs=args.epochs,
-                           batch=args.batch, lr=args.lr, eval_slices=args.eval_slices, tol=cfg3["tol"]))
-    net = UNet(K, 32, 4, max_batch=args.batch, H=256, W=256)
+    ny, nz = wl["ny"], wl["nz"]
+    out = dict(workload=args.workload,
+               config=dict(train_slices=args.train_slices, mask_sets=args.mask_sets, epochs=args.epochs,
+                           batch=args.batch, lr=args.lr, eval_slices=args.eval_slices or None, tol=ecfg["tol"],
+                           grid=[ny, nz], coils=wl["C"], T=ecfg["T"], K=K))
+    net = UNet(K, 32, 4, max_batch=args.batch, H=ny, W=nz)
     if args.params:
         net.set_params(np.load(args.params))
         out["train"] = dict(params=args.params)
     else:
         t0 = time.perf_counter()
-        b0, alpha = training_pairs(args.train_slices, args.train_seed, args.mask_sets, phi, cfg1)
+        b0, alpha = training_pairs(args.train_slices, args.train_seed, args.mask_sets, phi, tcfg, ny=ny, nz=nz,
+                                   C=wl["C"], chunk=wl["chunk"])
         out["pairs_s"] = time.perf_counter() - t0
         log(f"{args.train_slices} training pairs in {out['pairs_s']:.1f} s")
         net.set_params(net.init_params(args.train_seed))
@@ -197,14 +217,21 @@ def main():
             np.save(args.save_params, params)
         del b0, alpha
         torch.cuda.empty_cache()
+        if args.train_only:
+            json.dump(out, open(args.out, "w"), indent=1)
+            log(json.dumps(out))
+            net.close()
+            return
 
     # held-out evaluation volume
-    d = make_config(3, max_slices=args.eval_slices)
+    t0 = time.perf_counter()
+    d = make_config(wl["eval_cfg"], max_slices=args.eval_slices or None)
     cl = d["classes"][0]
+    log(f"evaluation volume ({cl.nslices} x {cl.ny}x{cl.nz} C{cl.ncoils}) generated in {time.perf_counter() - t0:.1f} s")
     runs = {}
     sols = {}
     for start in ("cold", "b0", "net"):
-        r, a, a0 = run_tolerance(phi, cl, cfg3, start, net)
+        r, a, a0 = run_tolerance(phi, cl, ecfg, start, net)
         runs[start] = r
         sols[start] = (a, a0)
         log(f"{start}: {r}")
@@ -218,7 +245,7 @@ def main():
     out["eval"] = runs
     out["start_error_vs_solution"] = dict(net=rel(a0n, ref), b0=rel(a0b, ref), zero=1.0)
     if args.plain:
-        r, _, _ = run_tolerance(phi, cl, cfg3, "cold", None, mode=T2S_PER_SLICE)
+        r, _, _ = run_tolerance(phi, cl, ecfg, "cold", None, mode=T2S_PER_SLICE)
         runs["plain"] = r
         log(f"plain (per-slice launches, cold): {r}")
         out["speedup_batched_net_vs_plain"] = r["s_per_volume"] / runs["net"]["s_per_volume"]

@@ -127,6 +127,25 @@ def test_admm_cfg0_parity():
     plan.close()
 
 
+@pytest.mark.parametrize("ny,nz,C,Tn,K", [(96, 32, 2, 6, 3), (320, 16, 2, 6, 4), (384, 32, 3, 8, 5)])
+def test_admm_ragged_column_workgroups(ny, nz, C, Tn, K):
+    """Column lengths whose pass-B workgroups do not fill whole waves (12 x 20 threads
+    for 320 and 384, 21 x 12 for 96): the CG step length is reduced over them."""
+    _say(f"ADMM parity ny={ny} nz={nz} C={C} T={Tn} K={K}, 4 outer x 3 CG, 2 slices")
+    phi, sens, masks, ksp = random_problem(ny + nz + K, ny, nz, C, Tn, K, S=2, frac=0.3)
+    plan = _plan(phi, [dict(ny=ny, nz=nz, ncoils=C, nslices=2, masks=masks)], lam=0.02, rho=0.1, n_outer=4,
+                 n_cg=3, seed=5)
+    plan.load(0, 0, sens, ksp)
+    plan.reconstruct()
+    got = plan.read(0, 0, 2)
+    plan.close()
+    for s in range(2):
+        ref = O.admm(ksp[s], sens[s], phi, masks.astype(bool), 0.02, 0.1, 8, 4, 3, 5, g=s)
+        e = rel(got[s], ref.alpha)
+        _say(f"  slice {s}: rel L2 {e:.3e}")
+        assert e < 1e-4, (s, e)
+
+
 def test_batched_equals_per_slice_bitwise():
     _say("batched vs per-slice launches, 3 slices 64x64")
     phi, sens, masks, ksp = random_problem(11, 64, 64, 3, 8, 3, S=3, frac=0.3)
