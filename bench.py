@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--fast-data", action="store_true",
                     help="random inputs of the workload's shapes (same masks) instead of the phantom; "
                          "for counter runs only: the solver's memory traffic does not depend on values")
+    ap.add_argument("--outer", type=int, default=0,
+                    help="override the workload's outer iteration count (counter runs only; 0: the workload's)")
     ap.add_argument("--traffic", type=str,
                     default=os.path.join(ROOT, "profiles", "hbm_traffic_vol320_256x256_c8_t80_k4.json"),
                     help="rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled HBM bytes per launch); ignored when "
@@ -150,6 +152,9 @@ def main():
         nprocs = args.cpu_procs or min(16, os.cpu_count() or 1)
         cpu = cpu_baseline(classes[0], phi, cfg, nprocs, args.cpu_outer)
         log(f"cpu baseline: {cpu['value']:.4f} slices/s ({cpu['sample']})")
+
+    if args.outer:
+        cfg["n_outer"] = args.outer
 
     import torch
 

@@ -85,10 +85,10 @@ __host__ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
     return z ^ (z >> 31);
 }
 
-// x * W_L^(+-e) with the twiddle read from the LDS table (0 <= e < L)
+// x * W_L^(+-e) with the twiddle read from the LDS table (0 <= e < L; the table's
+// entry 0 is exactly 1, so e = 0 needs no branch, which would diverge in a wave)
 template <bool INV>
 __device__ __forceinline__ float2 tw_mul(float2 x, const float2* tw, int e) {
-    if (e == 0) return x;
     float2 w = tw[e];
     if (INV) w.y = -w.y;
     return cmul(x, w);
@@ -96,6 +96,71 @@ __device__ __forceinline__ float2 tw_mul(float2 x, const float2* tw, int e) {
 
 template <int L>
 constexpr int rows_threads() { return kRowTile * RegGeom<L>::P; }
+// Occupancy targets of the row passes.  Left free, the register scheduler trades the
+// batched issue of a coil's loads for one more wave per SIMD and then waits on every
+// load in turn, which costs far more than the extra wave gains.
+constexpr int kPassAWavesPerSimd = 3;
+constexpr int kPassCWavesPerSimd = 2;
+
+// p = r (first) or r + beta p on the R1 positions R2 n1 + t of one row: every load is
+// issued before the first store (restrict: r and p never overlap), the new p is kept
+// in pv and stored; returns the thread's part of ||p||^2
+template <int R1, int R2>
+__device__ __forceinline__ double direction_update(const float2* __restrict__ r, float2* __restrict__ p, int t,
+                                                   int first, float beta, float2 (&pv)[R1]) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) pv[n1] = r[R2 * n1 + t];
+    if (!first) {
+        float2 po[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) po[n1] = p[R2 * n1 + t];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) pv[n1] = make_float2(pv[n1].x + beta * po[n1].x, pv[n1].y + beta * po[n1].y);
+    }
+    double pp = 0.0;
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+        p[R2 * n1 + t] = pv[n1];
+        pp += (double)pv[n1].x * pv[n1].x + (double)pv[n1].y * pv[n1].y;
+    }
+    return pp;
+}
+
+// CG update on the R1 positions R2 m of one row (pointers offset by the thread's t),
+// with w = acc + rho p in registers: x += alpha p, r -= alpha w; loads before stores (restrict: the three
+// vectors never overlap), in two halves to bound the registers; returns the thread's
+// part of ||r||^2
+template <int R1, int R2>
+__device__ __forceinline__ double cg_row_update(const float2 (&acc)[R1], const float2* __restrict__ p,
+                                                float2* __restrict__ x, float2* __restrict__ r, float rho,
+                                                float alpha) {
+    constexpr int H = R1 >= 8 ? R1 / 2 : R1;
+    double dot = 0.0;
+#pragma unroll
+    for (int h = 0; h < R1; h += H) {
+        float2 pv[H], xv[H], rv[H];
+#pragma unroll
+        for (int m = 0; m < H; ++m) pv[m] = p[R2 * (h + m)];
+#pragma unroll
+        for (int m = 0; m < H; ++m) xv[m] = x[R2 * (h + m)];
+#pragma unroll
+        for (int m = 0; m < H; ++m) rv[m] = r[R2 * (h + m)];
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const float2 w = make_float2(acc[h + m].x + rho * pv[m].x, acc[h + m].y + rho * pv[m].y);
+            xv[m].x += alpha * pv[m].x;
+            xv[m].y += alpha * pv[m].y;
+            rv[m].x -= alpha * w.x;
+            rv[m].y -= alpha * w.y;
+            dot += (double)rv[m].x * rv[m].x + (double)rv[m].y * rv[m].y;
+        }
+#pragma unroll
+        for (int m = 0; m < H; ++m) x[R2 * (h + m)] = xv[m];
+#pragma unroll
+        for (int m = 0; m < H; ++m) r[R2 * (h + m)] = rv[m];
+    }
+    return dot;
+}
 
 // ---------------------------------------------------------------------------
 // pass A: per (row tile, k): p = r + beta p, then per coil S_c p_k and the row FFT
@@ -104,7 +169,8 @@ constexpr int rows_threads() { return kRowTile * RegGeom<L>::P; }
 // the coalesced transposed stores.
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(rows_threads<L>()) void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
+__global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_eu(1, kPassAWavesPerSimd)))
+void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
                                                               int src_s0, int first, PartialSrc gc, PartialSrc gp,
                                                               int want_pp) {
     using G = RegGeom<L>;
@@ -134,24 +200,11 @@ __global__ __launch_bounds__(rows_threads<L>()) void k_passA(ClassArgs a, int s0
         beta = g0 > 0.0 ? (float)(g1 / g0) : 0.0f;
     }
     const size_t rowoff = (size_t)(y0 + r1) * L;
-    const float2* rs = src + ((size_t)(s - src_s0) * a.K + k) * N + rowoff;
-    float2* ps = a.p + ((size_t)s * a.K + k) * N + rowoff;
     float2 pv[R1];
     double pp = 0.0;
-    if (on1) {
-#pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) {
-            const int pos = R2 * n1 + t1;
-            float2 v = rs[pos];
-            if (!first) {
-                const float2 po = ps[pos];
-                v = make_float2(v.x + beta * po.x, v.y + beta * po.y);
-            }
-            ps[pos] = v;
-            pv[n1] = v;
-            pp += (double)v.x * v.x + (double)v.y * v.y;
-        }
-    }
+    if (on1)
+        pp = direction_update<R1, R2>(src + ((size_t)(s - src_s0) * a.K + k) * N + rowoff,
+                                      a.p + ((size_t)s * a.K + k) * N + rowoff, t1, first, beta, pv);
     if (want_pp) {
         const double tot = block_sum(pp, red);
         if (tid == 0) a.pa[(size_t)s * a.nrw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
@@ -368,7 +421,8 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
 // w = acc + rho p, a = gamma / <p, M p>, x += a p, r -= a w, partial <r, r>.
 // ---------------------------------------------------------------------------
 template <int L, int MODE>
-__global__ __launch_bounds__(rows_threads<L>()) void k_passC(ClassArgs a, int s0, float rho_add,
+__global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_eu(1, kPassCWavesPerSimd)))
+void k_passC(ClassArgs a, int s0, float rho_add,
                                                               float2* __restrict__ outp, int out_s0, PartialSrc gc,
                                                               int out_buf) {
     using G = RegGeom<L>;
@@ -439,28 +493,9 @@ __global__ __launch_bounds__(rows_threads<L>()) void k_passC(ClassArgs a, int s0
         const double pmp = partial_sum(PartialSrc{a.pb, a.npb, a.npb}, s) +
                            (double)a.rho * partial_sum(PartialSrc{a.pa, a.nrw, a.nrw}, s);
         const float alpha = (gamma > 0.0 && pmp > 0.0) ? (float)(gamma / pmp) : 0.0f;
-        const size_t vo = ((size_t)s * a.K + k) * N + rowoff;
-        const float2* pp = a.p + vo;
-        float2* xx = a.x + vo;
-        float2* rr = a.r + vo;
-        const float rho = a.rho;
+        const size_t vo = ((size_t)s * a.K + k) * N + rowoff + t1;
         double dot = 0.0;
-        if (on1) {
-#pragma unroll
-            for (int m2 = 0; m2 < R1; ++m2) {
-                const int pos = t1 + R2 * m2;
-                const float2 pv = pp[pos];
-                float2 xv = xx[pos], rv = rr[pos];
-                const float2 w = make_float2(acc[m2].x + rho * pv.x, acc[m2].y + rho * pv.y);
-                xv.x += alpha * pv.x;
-                xv.y += alpha * pv.y;
-                rv.x -= alpha * w.x;
-                rv.y -= alpha * w.y;
-                xx[pos] = xv;
-                rr[pos] = rv;
-                dot += (double)rv.x * rv.x + (double)rv.y * rv.y;
-            }
-        }
+        if (on1) dot = cg_row_update<R1, R2>(acc, a.p + vo, a.x + vo, a.r + vo, a.rho, alpha);
         const double tot = block_sum(dot, red);
         if (tid == 0) a.rr[((size_t)s * 2 + out_buf) * a.nrw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
     } else {
