@@ -104,6 +104,9 @@ def main():
                     help="launch schedule; 'graph' replays a captured outer iteration (no per-kernel events)")
     ap.add_argument("--schedule", type=str, default="0,1",
                     help="'auto' (autotuner), or CHUNK,STREAMS applied to every shape class")
+    ap.add_argument("--order", type=int, default=1,
+                    help="workgroup order flags of passes A / C (1: pass A, 2: pass C grouped by XCD); "
+                         "ignored with --schedule auto, which tunes it")
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(16, cores))")
     ap.add_argument("--cpu-outer", type=int, default=6, help="outer iterations of each oracle slice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -187,8 +190,10 @@ def main():
         ch, ns = (int(v) for v in args.schedule.split(","))
         for ci in range(len(classes)):
             T.t2s_set_schedule(plan.handle, ci, ch, ns)
+            T.t2s_set_order(plan.handle, ci, args.order)
     scheds = [T.t2s_get_schedule(plan.handle, ci) for ci in range(len(classes))]
-    log(f"schedules (chunk, streams): {scheds}")
+    orders = [T.t2s_get_order(plan.handle, ci) for ci in range(len(classes))]
+    log(f"schedules (chunk, streams): {scheds}, workgroup orders {orders}")
 
     def step():
         for ci in range(len(classes)):
@@ -238,6 +243,7 @@ def main():
             src = os.path.join(ROOT, "paper_1809_04195_amd", "csrc", "kernels.hip")
             cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
             same_sched = all(list(x) == [int(v) for v in tr.get("schedule", "0,1").split(",")] for x in scheds)
+            same_sched = same_sched and all(o == tr.get("order", 0) for o in orders)
             if tr.get("kernels_source_sha256_16") == cur and tr.get("workload") == cfg["name"] and same_sched:
                 t = tr["traffic"].get(dom)
                 traffic = None if t is None else int(t["bytes_per_launch"])
@@ -270,7 +276,7 @@ def main():
                    "T": int(phi.shape[0]), "K": int(phi.shape[1]), "outer": cfg["n_outer"], "cg": cfg["n_cg"],
                    "block": cfg["block"], "lambda": cfg["lam"], "rho": cfg["rho"], "mode": args.mode,
                    "step": "load_slices(device inputs) + reconstruct",
-                   "schedules": [list(x) for x in scheds]},
+                   "schedules": [list(x) for x in scheds], "orders": orders},
         "roofline": roofline,
         "solver_alg_gbs": round(tot_bytes / (elapsed * 1e9), 1),
         "kernels": {k: dict(launches=v["launches"], avg_ms=round(v["avg_ms"], 4),

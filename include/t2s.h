@@ -163,10 +163,20 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream);
 int t2s_set_schedule(t2s_plan* plan, int cls, int chunk, int nstreams);
 int t2s_get_schedule(const t2s_plan* plan, int cls, int* chunk, int* nstreams);
 
+/* Workgroup order of the row passes of class `cls`: with T2S_ORDER_XCD_PASS_A
+ * (T2S_ORDER_XCD_PASS_C) the workgroups of pass A (C) are dealt to the device's 8
+ * XCDs in contiguous runs of row tiles instead of round-robin.  Which streams
+ * better depends on the shape; same arithmetic, bitwise identical results. */
+#define T2S_ORDER_XCD_PASS_A 1
+#define T2S_ORDER_XCD_PASS_C 2
+int t2s_set_order(t2s_plan* plan, int cls, int order);
+int t2s_get_order(const t2s_plan* plan, int cls, int* order);
+
 /* Pick every class's schedule by timing `reps` CG steps of passes A/B/C per
  * candidate (all slices at once; chunks of 32/16/8/4/2 slices over 1, 2 or 4
- * streams) on the loaded slices, on `stream`.  Results are cached per process by
- * (ny, nz, ncoils, K, slices, device architecture).  Solver state is untouched.
+ * streams; then the workgroup orders of t2s_set_order with the best of those) on
+ * the loaded slices, on `stream`.  Results are cached per process by (ny, nz,
+ * ncoils, K, slices, device architecture).  Solver state is untouched.
  * Synchronises `stream`. */
 int t2s_autotune(t2s_plan* plan, int reps, void* stream);
 

@@ -40,6 +40,8 @@ T2S_ADJOINT = 3
 T2S_KERNEL_PASS_A = 0
 T2S_KERNEL_PASS_B = 1
 T2S_KERNEL_PASS_C = 2
+T2S_ORDER_XCD_PASS_A = 1
+T2S_ORDER_XCD_PASS_C = 2
 T2S_KERNEL_LLR = 3
 T2S_KERNEL_LOAD = 4
 KERNEL_NAMES = ("pass_a", "pass_b", "pass_c", "llr_admm", "load_adjoint")
@@ -120,6 +122,8 @@ _SIGS = {
     "t2s_get_schedule": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
                          ctypes.c_int),
     "t2s_autotune": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "t2s_set_order": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "t2s_get_order": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "t2s_unet_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                          ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "t2s_unet_destroy": ([ctypes.c_void_p], ctypes.c_int),
@@ -307,6 +311,16 @@ def t2s_get_schedule(plan, cls):
     a, b = ctypes.c_int(), ctypes.c_int()
     _check(lib().t2s_get_schedule(plan, cls, ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+def t2s_set_order(plan, cls, order):
+    return _check(lib().t2s_set_order(plan, cls, order))
+
+
+def t2s_get_order(plan, cls):
+    o = ctypes.c_int()
+    _check(lib().t2s_get_order(plan, cls, ctypes.byref(o)))
+    return o.value
 
 
 def t2s_autotune(plan, reps=3, stream=None):

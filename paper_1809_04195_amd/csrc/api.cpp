@@ -54,14 +54,18 @@ struct ClassPlan {
     std::vector<int> outer_run, k_freeze, converged;
     int chunk = 0;      // slices per pass launch (0: all slices of the class in one launch)
     int nstreams = 1;   // streams the chunks are spread over
+    int order = 0;      // workgroup order of passes A / C (T2S_ORDER_* flags)
     ClassArgs args{};
 };
 
 // Autotuned schedules, shared by every plan of the process, keyed by the shape of
 // the class and the device architecture.
 using SchedKey = std::tuple<int, int, int, int, int, std::string>;   // ny, nz, C, K, slices, arch
+struct Sched {
+    int chunk, nstreams, order;
+};
 std::mutex g_sched_mu;
-std::map<SchedKey, std::pair<int, int>> g_sched;
+std::map<SchedKey, Sched> g_sched;
 
 }  // namespace
 
@@ -136,6 +140,7 @@ void fill_args(t2s_plan* plan, ClassPlan& c) {
     a.gbase = c.gbase;
     a.hist_len = plan->hist_len;
     a.block = plan->prm.block;
+    a.order = c.order;
     a.tau = plan->prm.lambda / plan->prm.rho;
     a.rho = plan->prm.rho;
     a.seed = plan->prm.seed;
@@ -330,7 +335,8 @@ int run_outer_all(t2s_plan* plan, int mode, hipStream_t st) {
 
 std::string sched_signature(const t2s_plan* plan, int mode) {
     std::string k = std::to_string(mode);
-    for (const ClassPlan& c : plan->cls) k += "/" + std::to_string(c.chunk) + "x" + std::to_string(c.nstreams);
+    for (const ClassPlan& c : plan->cls)
+        k += "/" + std::to_string(c.chunk) + "x" + std::to_string(c.nstreams) + "o" + std::to_string(c.order);
     return k;
 }
 
@@ -805,6 +811,22 @@ int t2s_set_schedule(t2s_plan* plan, int cls, int chunk, int nstreams) {
     return 0;
 }
 
+int t2s_set_order(t2s_plan* plan, int cls, int order) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
+    if (order & ~(T2S_ORDER_XCD_PASS_A | T2S_ORDER_XCD_PASS_C)) return fail(T2S_EINVAL, "unknown order flags");
+    plan->cls[cls].order = order;
+    plan->cls[cls].args.order = order;
+    return 0;
+}
+
+int t2s_get_order(const t2s_plan* plan, int cls, int* order) {
+    if (!plan || !order) return fail(T2S_EINVAL, "NULL argument");
+    if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
+    *order = plan->cls[cls].order;
+    return 0;
+}
+
 int t2s_get_schedule(const t2s_plan* plan, int cls, int* chunk, int* nstreams) {
     if (!plan || !chunk || !nstreams) return fail(T2S_EINVAL, "NULL argument");
     if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
@@ -840,39 +862,56 @@ int t2s_autotune(t2s_plan* plan, int reps, void* stream) {
             std::lock_guard<std::mutex> lk(g_sched_mu);
             auto it = g_sched.find(key);
             if (it != g_sched.end()) {
-                c.chunk = it->second.first;
-                c.nstreams = it->second.second;
+                c.chunk = it->second.chunk;
+                c.nstreams = it->second.nstreams;
+                c.order = c.args.order = it->second.order;
                 continue;
             }
         }
-        // candidates: everything in one launch, or chunks of 32..2 slices over 1, 2 or 4 streams
-        std::vector<std::pair<int, int>> cands{{0, 1}};
-        for (int ch : {32, 16, 8, 4, 2})
-            if (ch < c.S)
-                for (int ns : {1, 2, 4}) cands.push_back({ch, ns});
-        float best = 1e30f;
-        std::pair<int, int> pick{0, 1};
-        for (auto cand : cands) {
-            // one warm-up, then `reps` timed CG steps (passes only, pass C writing M p to w:
-            // the solver state is untouched)
+        // candidates: everything in one launch, or chunks of 32..2 slices over 1, 2 or 4
+        // streams, in the plain workgroup order; then the XCD-grouped orders of passes A
+        // and C with the best of those
+        auto time_it = [&](const Sched& cand, float* ms) -> int {
+            c.args.order = cand.order;
+            // one warm-up, then `reps` timed CG steps (passes only, pass C writing M p to
+            // w: the solver state is untouched)
             for (int r = 0; r <= reps; ++r) {
                 if (r == 1) HIP_TRY(hipEventRecord(e0, st));
-                if (int e = run_passes(plan, c.args, 0, c.S, 0, cand.first, cand.second, false, st)) {
-                    g_prof = saved;
-                    return e;
-                }
+                if (int e = run_passes(plan, c.args, 0, c.S, 0, cand.chunk, cand.nstreams, false, st)) return e;
             }
             HIP_TRY(hipEventRecord(e1, st));
             HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                pick = cand;
+            HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+            return 0;
+        };
+        std::vector<Sched> cands{{0, 1, 0}};
+        for (int ch : {32, 16, 8, 4, 2})
+            if (ch < c.S)
+                for (int ns : {1, 2, 4}) cands.push_back({ch, ns, 0});
+        float best = 1e30f;
+        Sched pick{0, 1, 0};
+        for (int phase = 0; phase < 2; ++phase) {
+            if (phase == 1) {
+                cands.clear();
+                for (int o : {T2S_ORDER_XCD_PASS_A, T2S_ORDER_XCD_PASS_C, T2S_ORDER_XCD_PASS_A | T2S_ORDER_XCD_PASS_C})
+                    cands.push_back({pick.chunk, pick.nstreams, o});
+            }
+            for (const Sched& cand : cands) {
+                float ms = 0.f;
+                if (int e = time_it(cand, &ms)) {
+                    c.args.order = c.order;
+                    g_prof = saved;
+                    return e;
+                }
+                if (ms < best) {
+                    best = ms;
+                    pick = cand;
+                }
             }
         }
-        c.chunk = pick.first;
-        c.nstreams = pick.second;
+        c.chunk = pick.chunk;
+        c.nstreams = pick.nstreams;
+        c.order = c.args.order = pick.order;
         std::lock_guard<std::mutex> lk(g_sched_mu);
         g_sched[key] = pick;
     }

@@ -76,6 +76,23 @@ __device__ __forceinline__ double block_sum_ragged(double v, double* sh) {
     return r;
 }
 
+// Workgroup coordinates.  The dispatcher deals linear workgroup ids round-robin over
+// the 8 XCDs (each with its own L2); with `grouped`, id i is given the work item
+// (i mod 8) * (total / 8) + i / 8 (when 8 divides the total), so each XCD works
+// through a contiguous run of row tiles.  Which order streams better depends on the
+// shape, so it is a per-class schedule choice.
+struct Blk {
+    int x, y, z;
+};
+__device__ __forceinline__ Blk block_coords(bool grouped) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int total = gx * gy * gridDim.z;
+    if (!grouped || (total & 7) != 0) return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
+    int i = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    i = (i & 7) * (total >> 3) + (i >> 3);
+    return Blk{i % gx, (i / gx) % gy, i / (gx * gy)};
+}
+
 __device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[4 * s] != 0; }
 
 __host__ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
@@ -99,7 +116,10 @@ constexpr int rows_threads() { return kRowTile * RegGeom<L>::P; }
 // Occupancy targets of the row passes.  Left free, the register scheduler trades the
 // batched issue of a coil's loads for one more wave per SIMD and then waits on every
 // load in turn, which costs far more than the extra wave gains.
-constexpr int kPassAWavesPerSimd = 3;
+// Pass A: three waves while a thread holds at most 16 values per row, else two
+// (24 values per thread at ny = 384 need the larger register budget).
+template <int L>
+constexpr int passA_waves() { return RegGeom<L>::R1 <= 16 ? 3 : 2; }
 constexpr int kPassCWavesPerSimd = 2;
 
 // p = r (first) or r + beta p on the R1 positions R2 n1 + t of one row: every load is
@@ -169,10 +189,11 @@ __device__ __forceinline__ double cg_row_update(const float2 (&acc)[R1], const f
 // the coalesced transposed stores.
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_eu(1, kPassAWavesPerSimd)))
+__global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_eu(1, passA_waves<L>())))
 void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
                                                               int src_s0, int first, PartialSrc gc, PartialSrc gp,
                                                               int want_pp) {
+    const Blk bk = block_coords(a.order & kOrderXcdA);
     using G = RegGeom<L>;
     constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
     static_assert(NT % 64 == 0, "block_sum needs whole waves");
@@ -180,10 +201,10 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
     __shared__ float2 xb[RT * TB];
     __shared__ double red[16];
 
-    const int s = s0 + blockIdx.z;
+    const int s = s0 + bk.z;
     if (!slice_active(a, s)) return;
-    const int k = blockIdx.y;
-    const int y0 = blockIdx.x * RT;
+    const int k = bk.y;
+    const int y0 = bk.x * RT;
     const int ny = a.ny;
     const size_t N = (size_t)ny * L;
     const int tid = threadIdx.x;
@@ -207,7 +228,7 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
                                       a.p + ((size_t)s * a.K + k) * N + rowoff, t1, first, beta, pv);
     if (want_pp) {
         const double tot = block_sum(pp, red);
-        if (tid == 0) a.pa[(size_t)s * a.nrw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
+        if (tid == 0) a.pa[(size_t)s * a.nrw + bk.y * gridDim.x + bk.x] = tot;
     }
     __syncthreads();
     float2* xr1 = xb + r1 * TB;
@@ -217,7 +238,12 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
             const float2* S = a.sens + ((size_t)s * a.C + c) * N + rowoff;
             float2 v[R1];
 #pragma unroll
-            for (int n1 = 0; n1 < R1; ++n1) v[n1] = cmul(S[R2 * n1 + t1], pv[n1]);
+            for (int n1 = 0; n1 < R1; ++n1) v[n1] = S[R2 * n1 + t1];
+            // all of the coil's loads in flight before the first use (the scheduler would
+            // otherwise interleave load / wait / multiply to save registers)
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) v[n1] = cmul(v[n1], pv[n1]);
             dft_dir<R1, false>(v);
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) xr1[k1 * (R2 + 1) + t1] = tw_mul<false>(v[k1], tw, t1 * k1);
@@ -264,6 +290,8 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
     const size_t N = (size_t)L * nz;
     for (int i = tid; i < L; i += NT) tw[i] = a.twy[i];
     __syncthreads();
+    // columns past nz (last tile) read column 0 and are never stored: no selects between
+    // the loads and their first use, so the next coefficient's loads stay in flight
     float2* col = a.tmp + ((size_t)s * a.C + c) * (size_t)K * N + (size_t)(colok ? z : 0) * L;
     float2* xw = xb + w * TB;
 
@@ -271,7 +299,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
     float2 nxt[R1];   // next coefficient's column, loaded while the current one is transformed
     if (t < R2) {
 #pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) nxt[n1] = colok ? col[R2 * n1 + t] : make_float2(0.f, 0.f);
+        for (int n1 = 0; n1 < R1; ++n1) nxt[n1] = col[R2 * n1 + t];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -282,7 +310,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
             if (k + 1 < K) {
 #pragma unroll
                 for (int n1 = 0; n1 < R1; ++n1)
-                    nxt[n1] = colok ? col[(size_t)(k + 1) * N + R2 * n1 + t] : make_float2(0.f, 0.f);
+                    nxt[n1] = col[(size_t)(k + 1) * N + R2 * n1 + t];
             }
             dft_dir<R1, false>(v);
 #pragma unroll
@@ -394,7 +422,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
             float2 b[R2];
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2)
-                b[k2] = colok ? col[(size_t)k * N + t + R1 * k2] : make_float2(0.f, 0.f);
+                b[k2] = col[(size_t)k * N + t + R1 * k2];
             dft_dir<R2, true>(b);
 #pragma unroll
             for (int m1 = 0; m1 < R2; ++m1) xw[m1 * (R1 + 1) + t] = tw_mul<true>(b[m1], tw, t * m1);
@@ -425,6 +453,7 @@ __global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_
 void k_passC(ClassArgs a, int s0, float rho_add,
                                                               float2* __restrict__ outp, int out_s0, PartialSrc gc,
                                                               int out_buf) {
+    const Blk bk = block_coords(a.order & kOrderXcdC);
     using G = RegGeom<L>;
     constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
     static_assert(NT % 64 == 0, "block_sum needs whole waves");
@@ -432,10 +461,10 @@ void k_passC(ClassArgs a, int s0, float rho_add,
     __shared__ float2 xb[RT * TB];
     __shared__ double red[16];
 
-    const int s = s0 + blockIdx.z;
+    const int s = s0 + bk.z;
     if (!slice_active(a, s)) return;
-    const int k = blockIdx.y;
-    const int y0 = blockIdx.x * RT;
+    const int k = bk.y;
+    const int y0 = bk.x * RT;
     const int ny = a.ny;
     const size_t N = (size_t)ny * L;
     const int tid = threadIdx.x;
@@ -477,13 +506,28 @@ void k_passC(ClassArgs a, int s0, float rho_add,
         }
         __syncthreads();
         if (on1) {
-            float2 v[R1];
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) v[k1] = xr1[t1 * (R1 + 1) + k1];
-            dft_dir<R1, true>(v);
             const float2* S = a.sens + ((size_t)s * a.C + c) * N + rowoff;
+            if constexpr (R1 <= 24) {
+                // the coil's map is loaded first, in flight during the LDS reads and the
+                // FFT (R1 = 32 has no registers to spare for it)
+                float2 sv[R1];
 #pragma unroll
-            for (int m2 = 0; m2 < R1; ++m2) acc[m2] = cadd(acc[m2], cmulc(v[m2], S[t1 + R2 * m2]));
+                for (int m2 = 0; m2 < R1; ++m2) sv[m2] = S[t1 + R2 * m2];
+                __builtin_amdgcn_sched_barrier(0);
+                float2 v[R1];
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) v[k1] = xr1[t1 * (R1 + 1) + k1];
+                dft_dir<R1, true>(v);
+#pragma unroll
+                for (int m2 = 0; m2 < R1; ++m2) acc[m2] = cadd(acc[m2], cmulc(v[m2], sv[m2]));
+            } else {
+                float2 v[R1];
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) v[k1] = xr1[t1 * (R1 + 1) + k1];
+                dft_dir<R1, true>(v);
+#pragma unroll
+                for (int m2 = 0; m2 < R1; ++m2) acc[m2] = cadd(acc[m2], cmulc(v[m2], S[t1 + R2 * m2]));
+            }
         }
         __syncthreads();
     }
@@ -497,7 +541,7 @@ void k_passC(ClassArgs a, int s0, float rho_add,
         double dot = 0.0;
         if (on1) dot = cg_row_update<R1, R2>(acc, a.p + vo, a.x + vo, a.r + vo, a.rho, alpha);
         const double tot = block_sum(dot, red);
-        if (tid == 0) a.rr[((size_t)s * 2 + out_buf) * a.nrw + blockIdx.y * gridDim.x + blockIdx.x] = tot;
+        if (tid == 0) a.rr[((size_t)s * 2 + out_buf) * a.nrw + bk.y * gridDim.x + bk.x] = tot;
     } else {
         float2* out = outp + ((size_t)(s - out_s0) * a.K + k) * N + rowoff;
         if (on1) {

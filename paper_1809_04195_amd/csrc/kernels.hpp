@@ -26,6 +26,8 @@ struct ClassArgs {
     int gbase;                   // global index of the class's slice 0
     int hist_len;                // outer-iteration capacity of the residual history
     int block;                   // LLR block edge
+    int order;                   // workgroup order of the row passes: bit 0 pass A, bit 1
+                                 // pass C grouped by XCD (kOrderXcdA / kOrderXcdC)
     float tau, rho;              // LLR threshold lambda / rho, ADMM penalty
     uint64_t seed;
     const float* psi;            // upper triangle of Psi, uncentred, / (ny nz), in pass-B order:
@@ -49,6 +51,9 @@ struct ClassArgs {
     double* hist;                // [S][hist_len][8] per-outer residual sums
     int* state;                  // [S][4]: active flag, frozen outer index (-1: none), outer counter, spare
 };
+
+constexpr int kOrderXcdA = 1;
+constexpr int kOrderXcdC = 2;
 
 // LLR kernel flavours
 enum LlrMode { kLlrAdmm = 0, kLlrProx = 1 };

@@ -108,7 +108,8 @@ def traffic(args):
     wscale = COPY_PROBE_BYTES / (wcopy * 1024.0)
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
     res = {"kernels_source_sha256_16": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16],
-           "workload": args.workload, "schedule": args.schedule, "fetch_scale": fscale, "write_scale": wscale,
+           "workload": args.workload, "schedule": args.schedule, "order": args.order, "fetch_scale": fscale,
+           "write_scale": wscale,
            "copy_probe_bytes": COPY_PROBE_BYTES, "traffic": {}}
     for fam in ("pass_a", "pass_b", "pass_c", "llr_admm"):
         if fam in fe and fam in wr:
@@ -187,6 +188,7 @@ def main():
     t.add_argument("--write", required=True)
     t.add_argument("--workload", required=True)
     t.add_argument("--schedule", default="0,1")
+    t.add_argument("--order", type=int, default=0)
     t.add_argument("--out", default="")
     c = sub.add_parser("counters")
     c.add_argument("dirs", nargs="+")

@@ -133,6 +133,23 @@ def test_plan_state_errors_without_gpu():
     assert L.t2s_plan_destroy(h) == 0
 
 
+def test_schedule_and_order_validation():
+    phi = _phi()
+    cls, masks = _classes()
+    code, h = _create(phi, cls)
+    assert code == 0
+    L = T.lib()
+    assert L.t2s_set_order(h, 0, 4) == T.T2S_EINVAL
+    assert L.t2s_set_order(h, 1, 0) == T.T2S_EINVAL
+    assert L.t2s_set_order(h, 0, T.T2S_ORDER_XCD_PASS_A | T.T2S_ORDER_XCD_PASS_C) == 0
+    assert T.t2s_get_order(h, 0) == 3
+    assert L.t2s_set_schedule(h, 0, -1, 1) == T.T2S_EINVAL
+    assert L.t2s_set_schedule(h, 0, 2, 9) == T.T2S_EINVAL
+    assert L.t2s_set_schedule(h, 0, 2, 3) == 0
+    assert T.t2s_get_schedule(h, 0) == (2, 3)
+    T.t2s_plan_destroy(h)
+
+
 def test_psi_table_matches_oracle():
     phi = _phi(T_=7, K=3)
     ny, nz = 32, 48

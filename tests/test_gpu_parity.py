@@ -264,6 +264,23 @@ def test_chunked_schedules_bitwise():
         assert np.array_equal(got, ref), sched
 
 
+def test_workgroup_orders_bitwise():
+    _say("XCD-grouped workgroup orders of passes A and C vs the plain order")
+    phi, sens, masks, ksp = random_problem(34, 64, 64, 3, 8, 3, S=8, frac=0.3)
+    outs = []
+    for order in range(4):
+        plan = _plan(phi, [dict(ny=64, nz=64, ncoils=3, nslices=8, masks=masks)], lam=0.05, rho=0.1, n_outer=4,
+                     n_cg=3, seed=17)
+        T.t2s_set_order(plan.handle, 0, order)
+        assert T.t2s_get_order(plan.handle, 0) == order
+        plan.load(0, 0, sens, ksp)
+        plan.reconstruct(T.T2S_BATCHED_GRAPH if order % 2 else T.T2S_BATCHED)
+        outs.append(plan.read(0, 0, 8))
+        plan.close()
+    for order in range(1, 4):
+        assert np.array_equal(outs[order], outs[0]), order
+
+
 def test_graph_replay_matches_eager():
     import torch
     _say("hipGraph replay of the outer iteration vs eager launches, 3 replays with eager work between")
