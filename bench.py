@@ -32,36 +32,6 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# ---------------------------------------------------------------------------
-# algorithmic bytes per slice of each kernel family (one launch covers all slices)
-# ---------------------------------------------------------------------------
-
-
-def alg_bytes_per_slice(kind, ny, nz, C, K, n_cg):
-    N = ny * nz
-    c8 = 8.0 * N
-    if kind == "pass_a":       # read r (+ p), S; write p, C K transformed rows
-        first = c8 * (2 * K + C + C * K)
-        rest = c8 * (3 * K + C + C * K)
-        return (first + (n_cg - 1) * rest) / n_cg
-    if kind == "pass_b":       # read + write the C K intermediate, read Psi (upper triangle, fp32)
-        return c8 * 2 * C * K + 4.0 * N * K * (K + 1) / 2
-    if kind == "pass_c":       # read C K intermediate, S, p, x, r; write x, r (CG update fused)
-        return c8 * (C * K + C + 5 * K)
-    if kind == "llr_admm":     # read alpha, u, z, r; write z, u, r
-        return c8 * 7 * K
-    if kind == "load_adjoint":
-        return None
-    raise KeyError(kind)
-
-
-# ---------------------------------------------------------------------------
-# CPU baseline: the FP64 oracle on the host cores, one slice per process
-# ---------------------------------------------------------------------------
-
-_CPU = {}
-
-
 def _oracle_job(i):
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import t2s as O
@@ -162,6 +132,7 @@ def main():
     import torch
 
     import paper_1809_04195_amd as T
+    from paper_1809_04195_amd.traffic_model import alg_bytes_per_slice
 
     assert torch.cuda.is_available(), "no GPU"
     dev = torch.device("cuda:0")

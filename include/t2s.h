@@ -101,9 +101,10 @@ typedef struct t2s_slice_report {
     int outer_iterations;  /* outer iterations run                                   */
     int k_freeze;          /* outer index whose shift was frozen (-1: never)         */
     int converged;         /* tolerance mode: 1 if max(r_p, r_d) <= tol             */
-    double r_primal;       /* ||alpha - z|| / max(||alpha||, ||z||) after the last outer */
-    double r_dual;         /* ||z - z_prev|| / max(||alpha||, ||z||) (dual residual   */
-                           /* rho (z - z_prev) relative to rho times the solution scale) */
+    double r_primal;       /* ||alpha - z|| / d after the last outer iteration, with */
+                           /* d = max(||alpha||, ||z||, 0.01 ||b0||) (0 when d = 0)   */
+    double r_dual;         /* ||z - z_prev|| / d (dual residual rho (z - z_prev)      */
+                           /* relative to rho times the solution scale)               */
 } t2s_slice_report;
 
 typedef struct t2s_plan t2s_plan;
@@ -151,8 +152,12 @@ int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* a
 /* Run ADMM on every loaded slice.  mode = T2S_BATCHED or T2S_PER_SLICE (same
  * arithmetic, different launch schedule).  Fixed mode (tol == 0) is fully
  * asynchronous.  Tolerance mode synchronises `stream` every check_every outer
- * iterations to read the per-slice residuals, and returns T2S_WNOTCONVERGED if a
- * slice reached n_outer without meeting tol. */
+ * iterations to read the per-slice residuals and decides per slice, in this order:
+ * stop if max(r_p, r_d) <= tol; else freeze the block shift at the current draw if
+ * max(r_p, r_d) fell by less than freeze_stall over freeze_window iterations (with a
+ * new shift every iteration ADMM has no fixed point and the residual stalls well
+ * above tol).  Returns T2S_WNOTCONVERGED if a slice reached n_outer without meeting
+ * tol. */
 int t2s_reconstruct(t2s_plan* plan, int mode, void* stream);
 
 /* Batching schedule of class `cls`: pass launches cover `chunk` slices (0 = all
@@ -258,7 +263,8 @@ int t2s_unet_bind_workspace(t2s_unet* net, void* device_ptr, size_t bytes, void*
 int t2s_unet_set_params(t2s_unet* net, const float* params, void* stream);
 int t2s_unet_get_params(t2s_unet* net, float* params, void* stream);
 /* alpha0 = s (x + net(x)) with x = pack(b0) / s; b0, alpha0: device complex64
- * [B][K][H][W], 1 <= B <= max_batch.  Asynchronous. */
+ * [B][K][H][W], 1 <= B <= max_batch.  An all-zero slice (s = 0) gets alpha0 = 0.
+ * Asynchronous. */
 int t2s_unet_forward(t2s_unet* net, const void* b0, void* alpha0, int B, void* stream);
 /* One Adam step (lr; beta 0.9 / 0.999, eps 1e-8) on the mean squared error between
  * x + net(x) and target / s (target: device complex64 [B][K][H][W]).  If `loss` is not

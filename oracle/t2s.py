@@ -282,13 +282,19 @@ class AdmmResult:
         self.n_outer = n_outer          # outer iterations run
 
 
-def admm_residuals(alpha, z, z_prev, u, rho):
+# Floor of the residual scale, as a fraction of ||b0|| = ||A^H y||: a slice whose
+# solution is zero (every block below the threshold) would otherwise divide by a
+# vanishing ||alpha||.
+RESIDUAL_SCALE_FLOOR = 0.01
+
+
+def admm_residuals(alpha, z, z_prev, u, rho, b0_norm=0.0):
     """Primal residual alpha - z and dual residual rho (z - z_prev) (Boyd et al.,
     Sec. 3.3), both relative to the scale of the solution:
-    r_p = ||alpha - z|| / max(||alpha||, ||z||),
-    r_d = rho ||z - z_prev|| / (rho max(||alpha||, ||z||)).   (0 when alpha = z = 0)"""
+    r_p = ||alpha - z|| / d,  r_d = rho ||z - z_prev|| / (rho d),
+    d = max(||alpha||, ||z||, RESIDUAL_SCALE_FLOOR ||b0||)   (0 when d = 0)"""
     na, nz = np.linalg.norm(alpha), np.linalg.norm(z)
-    den = max(na, nz)
+    den = max(na, nz, RESIDUAL_SCALE_FLOOR * b0_norm)
     rp = np.linalg.norm(alpha - z) / den if den > 0 else 0.0
     rd = np.linalg.norm(z - z_prev) / den if den > 0 else 0.0
     return rp, rd
@@ -305,9 +311,12 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
       3. u <- u + alpha - z
     Fixed mode (tol == 0): exactly n_outer iterations, a new shift every iteration.
     Tolerance mode (tol > 0): decisions are taken after outer iterations k with
-    (k + 1) % check_every == 0, in this order: stop if the shift was already frozen
-    and max(r_p, r_d) <= tol; else freeze at shift k if max(r_p, r_d) at k exceeds
-    (1 - freeze_stall) times its value at k - freeze_window.  n_outer is the cap.
+    (k + 1) % check_every == 0, in this order: stop if max(r_p, r_d) <= tol; else,
+    if the shift is not frozen yet, freeze it at shift k if max(r_p, r_d) at k
+    exceeds (1 - freeze_stall) times its value at k - freeze_window.  n_outer is the
+    cap.  (Under random shifts the residual stalls well above tol, so the stop
+    normally comes after the freeze; a slice whose residual is exactly zero, such as
+    one with no signal, stops at the first check.)
     ``replay`` = (k_freeze, n_run) imposes another run's decisions instead.
     """
     sens = np.asarray(sens, dtype=np.complex128)
@@ -316,6 +325,7 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
     C, Ny, Nz = sens.shape
     tau = lam / rho
     b0 = adjoint(samples, sens, phi, masks)
+    b0_norm = np.linalg.norm(b0)
     if normal == "psi":
         psi = space_time_kernel(phi, masks)
 
@@ -345,7 +355,7 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
             shift = block_shift(seed, g, k, b)
         z = llr_prox(alpha + u, tau, shift, b)
         u = u + alpha - z
-        rp, rd = admm_residuals(alpha, z, z_prev, u, rho)
+        rp, rd = admm_residuals(alpha, z, z_prev, u, rho, b0_norm)
         history.append(dict(k=k, shift=shift, r_primal=rp, r_dual=rd, res=max(rp, rd)))
         k += 1
         if replay is not None:
@@ -357,7 +367,7 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
             continue
         if tol > 0 and k % check_every == 0:
             res = history[-1]["res"]
-            if k_freeze >= 0 and res <= tol:
+            if res <= tol:
                 break
             if k_freeze < 0 and k - 1 >= freeze_window:
                 if res > (1.0 - freeze_stall) * history[k - 1 - freeze_window]["res"]:

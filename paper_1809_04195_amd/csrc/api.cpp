@@ -48,7 +48,7 @@ struct ClassPlan {
     std::vector<int> row_ptr, ent_t, ent_p;
     std::vector<float> twy, twz;            // interleaved (re, im)
     size_t o_psi = 0, o_twy = 0, o_twz = 0, o_phi = 0, o_rowptr = 0, o_entt = 0, o_entp = 0;
-    size_t o_sens = 0, o_ksp = 0, o_vec[7] = {}, o_tmp = 0, o_pa = 0, o_pb = 0, o_rr = 0, o_g0 = 0, o_llr = 0,
+    size_t o_sens = 0, o_ksp = 0, o_vec[7] = {}, o_tmp = 0, o_pa = 0, o_pb = 0, o_rr = 0, o_g0 = 0, o_b0n = 0, o_llr = 0,
            o_hist = 0, o_state = 0;
     std::vector<int> loaded;
     std::vector<int> outer_run, k_freeze, converged;
@@ -165,6 +165,7 @@ void fill_args(t2s_plan* plan, ClassPlan& c) {
     a.pb = (double*)(b + c.o_pb);
     a.rr = (double*)(b + c.o_rr);
     a.g0 = (double*)(b + c.o_g0);
+    a.b0n = (double*)(b + c.o_b0n);
     a.llr = (double*)(b + c.o_llr);
     a.hist = (double*)(b + c.o_hist);
     a.state = (int*)(b + c.o_state);
@@ -387,10 +388,13 @@ int ensure_graph(t2s_plan* plan, int mode) {
 
 // relative primal / dual residuals from the per-outer sums (alpha - z, z - z_prev,
 // alpha, z, u, r squared norms): both relative to max(||alpha||, ||z||)
-void residuals_from_hist(const double* h, double rho, double* rp, double* rd) {
-    (void)rho;
+// Relative ADMM residuals of one outer iteration from its summed squares (h[0] =
+// ||alpha - z||^2, h[1] = ||z - z_prev||^2, h[2] = ||alpha||^2, h[3] = ||z||^2),
+// scaled by max(||alpha||, ||z||, kResidualScaleFloor ||b0||)
+constexpr double kResidualScaleFloor = 0.01;
+void residuals_from_hist(const double* h, double b0_norm, double* rp, double* rd) {
     const double na = std::sqrt(h[2]), nzz = std::sqrt(h[3]);
-    const double den = std::max(na, nzz);
+    const double den = std::max(std::max(na, nzz), kResidualScaleFloor * b0_norm);
     *rp = den > 0 ? std::sqrt(h[0]) / den : 0.0;
     *rd = den > 0 ? std::sqrt(h[1]) / den : 0.0;
 }
@@ -554,6 +558,7 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.o_pb = take((size_t)c.S * c.npb * 8);
         c.o_rr = take((size_t)c.S * 2 * c.nrw * 8);
         c.o_g0 = take((size_t)c.S * c.nllr * 8);
+        c.o_b0n = take((size_t)c.S * c.nllr * 8);
         c.o_llr = take((size_t)c.S * c.nllr * 8 * 8);
         c.o_hist = take((size_t)c.S * plan->hist_len * 8 * 8);
         c.o_state = take((size_t)c.S * 4 * 4);
@@ -752,6 +757,19 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
         std::vector<std::vector<int>> active(plan->cls.size());
         for (size_t ci = 0; ci < plan->cls.size(); ++ci) active[ci].assign(plan->cls[ci].S, 1);
         std::vector<double> hbuf;
+        // ||b0|| of every slice (partials written when the slice was loaded)
+        std::vector<std::vector<double>> b0norm(plan->cls.size());
+        for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
+            const ClassPlan& c = plan->cls[ci];
+            std::vector<double> part((size_t)c.S * c.nllr);
+            HIP_TRY(hipMemcpy(part.data(), c.args.b0n, part.size() * 8, hipMemcpyDeviceToHost));
+            b0norm[ci].assign(c.S, 0.0);
+            for (int s = 0; s < c.S; ++s) {
+                double acc = 0.0;
+                for (int j = 0; j < c.nllr; ++j) acc += part[(size_t)s * c.nllr + j];
+                b0norm[ci][s] = std::sqrt(acc);
+            }
+        }
         int k = 0;
         bool any = true;
         while (k < prm.n_outer && any) {
@@ -769,16 +787,16 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
                     c.outer_run[s] = k;
                     double rp, rd;
                     const double* h = &hbuf[((size_t)s * plan->hist_len + (k - 1)) * 8];
-                    residuals_from_hist(h, prm.rho, &rp, &rd);
+                    residuals_from_hist(h, b0norm[ci][s], &rp, &rd);
                     const double r = std::max(rp, rd);
                     bool stop = false;
-                    if (c.k_freeze[s] >= 0 && r <= prm.tol) {
+                    if (r <= prm.tol) {
                         stop = true;
                         c.converged[s] = 1;
                     } else if (c.k_freeze[s] < 0 && k - 1 >= prm.freeze_window) {
                         double rpo, rdo;
                         residuals_from_hist(&hbuf[((size_t)s * plan->hist_len + (k - 1 - prm.freeze_window)) * 8],
-                                            prm.rho, &rpo, &rdo);
+                                            b0norm[ci][s], &rpo, &rdo);
                         if (r > (1.0 - prm.freeze_stall) * std::max(rpo, rdo)) {
                             c.k_freeze[s] = k - 1;
                             HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 1, k - 1, -1, st));
@@ -959,7 +977,11 @@ int t2s_get_slice_report(const t2s_plan* plan, int cls, int slice, t2s_slice_rep
         HIP_TRY(hipStreamSynchronize(plan->last_stream));
         HIP_TRY(hipMemcpy(h, c.args.hist + ((size_t)slice * plan->hist_len + (k - 1)) * 8, sizeof(h),
                           hipMemcpyDeviceToHost));
-        residuals_from_hist(h, plan->prm.rho, &out->r_primal, &out->r_dual);
+        std::vector<double> part(c.nllr);
+        HIP_TRY(hipMemcpy(part.data(), c.args.b0n + (size_t)slice * c.nllr, part.size() * 8, hipMemcpyDeviceToHost));
+        double bb = 0.0;
+        for (double v : part) bb += v;
+        residuals_from_hist(h, std::sqrt(bb), &out->r_primal, &out->r_dual);
     }
     return 0;
 }

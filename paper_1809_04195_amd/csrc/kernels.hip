@@ -606,19 +606,23 @@ __global__ __launch_bounds__(kThreads) void k_init(ClassArgs a, int s0, const fl
     const size_t n = (size_t)a.K * a.ny * a.nz;
     const size_t base = (size_t)s * n;
     const float2* a0 = alpha0 ? alpha0 + (size_t)(s - s0) * n : nullptr;
-    double dot = 0.0;
+    double dot = 0.0, bb = 0.0;
     for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (size_t)gridDim.x * kThreads) {
         const float2 xv = a0 ? a0[e] : make_float2(0.f, 0.f);
-        float2 rv = a.b0[base + e];
+        const float2 bv = a.b0[base + e];
+        float2 rv = bv;
         if (sub_w) rv = csub(rv, a.w[base + e]);
         a.x[base + e] = xv;
         a.z[base + e] = xv;
         a.u[base + e] = make_float2(0.f, 0.f);
         a.r[base + e] = rv;
         dot += (double)rv.x * rv.x + (double)rv.y * rv.y;
+        bb += (double)bv.x * bv.x + (double)bv.y * bv.y;
     }
     const double tot = block_sum(dot, red);
     if (threadIdx.x == 0) a.g0[(size_t)s * a.nllr + blockIdx.x] = tot;
+    const double tb = block_sum(bb, red);
+    if (threadIdx.x == 0) a.b0n[(size_t)s * a.nllr + blockIdx.x] = tb;
 }
 
 // ---------------------------------------------------------------------------

@@ -47,6 +47,7 @@ struct ClassArgs {
     double* pb;                  // [S][npb]    k-space partials of <p, A^H A p> (pass B)
     double* rr;                  // [S][2][nrw] <r, r> partials of the CG update (pass C)
     double* g0;                  // [S][nllr]   <r, r> at the start of an outer iteration
+    double* b0n;                 // [S][nllr]   ||b0||^2 partials (written with the state init)
     double* llr;                 // [S][nllr][8] residual partial sums of the z-step
     double* hist;                // [S][hist_len][8] per-outer residual sums
     int* state;                  // [S][4]: active flag, frozen outer index (-1: none), outer counter, spare
@@ -80,7 +81,8 @@ hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float r
 hipError_t launch_passC_cg(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st);
 // tmp[c][k] = projected, sign-modulated, uncentred k-space of the samples (adjoint input)
 hipError_t launch_project(const ClassArgs& a, int s0, int count, hipStream_t st);
-// x = z = alpha0 (or 0), u = 0, r = b0 - (sub_w ? w : 0); partial <r, r> into g0
+// x = z = alpha0 (or 0), u = 0, r = b0 - (sub_w ? w : 0); partial <r, r> into g0 and
+// ||b0||^2 into b0n
 hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alpha0, int sub_w, hipStream_t st);
 // ADMM z/u/r update with the shift of the slice's outer counter (mode kLlrAdmm;
 // k unused), or out = prox(in) at the explicit shift (mode kLlrProx)

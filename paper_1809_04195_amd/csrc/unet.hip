@@ -356,7 +356,7 @@ __global__ void k_slice_scale(const float2* b0, int K, int N, float* scale) {
         if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) scale[s] = red[0] > 0.f ? red[0] : 1.f;
+    if (threadIdx.x == 0) scale[s] = red[0];   // 0 for an all-zero slice
 }
 
 // complex [S][K][H][W] / scale[s] -> fp32 [S][H][W][2K] and bf16 [S][H][W][ldb] (zero padded)
@@ -365,7 +365,7 @@ __global__ void k_pack(const float2* src, const float* scale, int K, int HW, flo
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (i >= (size_t)HW) return;
-    const float inv = 1.f / scale[s];
+    const float inv = scale[s] > 0.f ? 1.f / scale[s] : 0.f;
     const size_t p = (size_t)s * HW + i;
     for (int k = 0; k < K; ++k) {
         const float2 v = src[((size_t)s * K + k) * HW + i];
@@ -383,7 +383,8 @@ __global__ void k_pack(const float2* src, const float* scale, int K, int HW, flo
     (void)n;
 }
 
-// alpha0[s][k][i] = scale[s] (x + y)[s][i][2k, 2k+1]
+// alpha0[s][k][i] = scale[s] (x + y)[s][i][2k, 2k+1]  (an all-zero input slice has
+// scale 0 and gets alpha0 = 0: the solution for no data is zero)
 __global__ void k_unpack(const float* x32, const float* y32, int ldy, const float* scale, int K, int HW, float2* dst) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;

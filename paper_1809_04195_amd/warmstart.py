@@ -20,7 +20,9 @@ import time
 
 import numpy as np
 
-from . import (T2S_ADJOINT, T2S_ALPHA, T2S_BATCHED, T2S_BATCHED_GRAPH, T2S_PER_SLICE, Plan, UNet, t2s_autotune)
+from . import (T2S_ADJOINT, T2S_ALPHA, T2S_BATCHED, T2S_BATCHED_GRAPH, T2S_PER_SLICE, Plan, UNet, t2s_autotune,
+               t2s_get_order, t2s_get_schedule)
+from .traffic_model import bytes_per_outer
 
 
 def log(msg):
@@ -126,6 +128,7 @@ def run_tolerance(phi, cl, cfg, start, net=None, batch=16, mode=T2S_BATCHED_GRAP
     dksp = torch.from_numpy(np.ascontiguousarray(cl.ksp)).cuda()
     plan.load(0, 0, dsens, dksp)
     t2s_autotune(plan.handle, 2)
+    sched, order = t2s_get_schedule(plan.handle, 0), t2s_get_order(plan.handle, 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.load(0, 0, dsens, dksp)
@@ -146,10 +149,12 @@ def run_tolerance(phi, cl, cfg, start, net=None, batch=16, mode=T2S_BATCHED_GRAP
     alpha = plan.read(0, 0, S, T2S_ALPHA, device=True)
     plan.close()
     its = np.array([r["outer_iterations"] for r in reps])
-    res = dict(start=start, mode="per_slice" if mode == T2S_PER_SLICE else "batched_graph", s_per_volume=wall, slices_per_s=S / wall, outer_mean=float(its.mean()),
-               outer_max=int(its.max()), outer_min=int(its.min()),
+    alg = float(its.sum()) * bytes_per_outer(cl.ny, cl.nz, cl.ncoils, phi.shape[1], cfg["n_cg"])
+    res = dict(start=start, mode="per_slice" if mode == T2S_PER_SLICE else "batched_graph", s_per_volume=wall,
+               slices_per_s=S / wall, outer_mean=float(its.mean()), outer_max=int(its.max()), outer_min=int(its.min()),
                converged=int(sum(r["converged"] for r in reps)), slices=S, code=int(code),
-               final_residual_max=float(max(max(r["r_primal"], r["r_dual"]) for r in reps)))
+               final_residual_max=float(max(max(r["r_primal"], r["r_dual"]) for r in reps)),
+               solver_alg_gbs=alg / wall / 1e9, schedule=list(sched), order=order)
     return res, alpha, a0
 
 
@@ -178,6 +183,8 @@ def main():
     ap.add_argument("--params", type=str, default="", help="trained parameters (.npy): skip data generation and training")
     ap.add_argument("--train-only", action="store_true", help="stop after training (parameters saved)")
     ap.add_argument("--plain", action="store_true", help="also run the plain solver: per-slice launches, cold start")
+    ap.add_argument("--starts", type=str, default="cold,b0,net",
+                    help="batched runs to make (comma list of cold, b0, net; empty with --plain: plain only)")
     args = ap.parse_args()
     wl = WORKLOADS[args.workload]
     args.out = args.out or f"gpurun_out/warmstart_{args.workload}.json"
@@ -230,30 +237,34 @@ def main():
     log(f"evaluation volume ({cl.nslices} x {cl.ny}x{cl.nz} C{cl.ncoils}) generated in {time.perf_counter() - t0:.1f} s")
     runs = {}
     sols = {}
-    for start in ("cold", "b0", "net"):
+    starts = [x for x in args.starts.split(",") if x]
+    for start in starts:
         r, a, a0 = run_tolerance(phi, cl, ecfg, start, net)
         runs[start] = r
         sols[start] = (a, a0)
         log(f"{start}: {r}")
-    ref = sols["cold"][0]
-    a0n = sols["net"][1]
-    a0b = sols["b0"][1]
 
     def rel(x, y):
         return float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
 
     out["eval"] = runs
-    out["start_error_vs_solution"] = dict(net=rel(a0n, ref), b0=rel(a0b, ref), zero=1.0)
+    full = all(x in sols for x in ("cold", "b0", "net"))
+    if full:
+        ref = sols["cold"][0]
+        a0n = sols["net"][1]
+        out["start_error_vs_solution"] = dict(net=rel(a0n, ref), b0=rel(sols["b0"][1], ref), zero=1.0)
     if args.plain:
         r, _, _ = run_tolerance(phi, cl, ecfg, "cold", None, mode=T2S_PER_SLICE)
         runs["plain"] = r
         log(f"plain (per-slice launches, cold): {r}")
-        out["speedup_batched_net_vs_plain"] = r["s_per_volume"] / runs["net"]["s_per_volume"]
-        out["speedup_batched_cold_vs_plain"] = r["s_per_volume"] / runs["cold"]["s_per_volume"]
-    out["speedup_net_vs_cold"] = runs["cold"]["s_per_volume"] / runs["net"]["s_per_volume"]
-    out["speedup_b0_vs_cold"] = runs["cold"]["s_per_volume"] / runs["b0"]["s_per_volume"]
-    out["outer_saved_net_vs_cold"] = runs["cold"]["outer_mean"] - runs["net"]["outer_mean"]
-    if args.save_samples:
+        if full:
+            out["speedup_batched_net_vs_plain"] = r["s_per_volume"] / runs["net"]["s_per_volume"]
+            out["speedup_batched_cold_vs_plain"] = r["s_per_volume"] / runs["cold"]["s_per_volume"]
+    if full:
+        out["speedup_net_vs_cold"] = runs["cold"]["s_per_volume"] / runs["net"]["s_per_volume"]
+        out["speedup_b0_vs_cold"] = runs["cold"]["s_per_volume"] / runs["b0"]["s_per_volume"]
+        out["outer_saved_net_vs_cold"] = runs["cold"]["outer_mean"] - runs["net"]["outer_mean"]
+    if args.save_samples and full:
         sel = np.linspace(0, cl.nslices - 1, args.save_samples + 2).round().astype(int)[1:-1]
         np.savez(os.path.splitext(args.out)[0] + "_samples.npz", slices=sel,
                  index=cl.slice_index[sel], net=a0n[sel].cpu().numpy(), solution=ref[sel].cpu().numpy())

@@ -227,6 +227,28 @@ def test_tolerance_mode_replay_parity():
     plan.close()
 
 
+def test_tolerance_mode_empty_slice_stops_first_check():
+    _say("tolerance mode: a slice with no signal next to a normal one")
+    cfg, phi, cl = _cfg0()
+    m = cl.masks.astype(bool)
+    sens = np.concatenate([cl.sens, cl.sens])
+    ksp = np.concatenate([cl.ksp, np.zeros_like(cl.ksp)])
+    plan = _plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=2, masks=cl.masks)],
+                 lam=cfg["lam"], rho=cfg["rho"], n_outer=300, n_cg=5, seed=cfg["seed"], tol=1e-4,
+                 freeze_window=5, freeze_stall=0.05, check_every=5)
+    plan.load(0, 0, sens, ksp)
+    plan.reconstruct()
+    r0, r1 = plan.report(0, 0), plan.report(0, 1)
+    _say(f"  normal slice: outer {r0['outer_iterations']} freeze {r0['k_freeze']}; empty slice: {r1}")
+    assert r1["outer_iterations"] == 5 and r1["converged"] == 1 and r1["r_primal"] == 0.0
+    got = plan.read(0, 0, 2)
+    assert not got[1].any()
+    ref = O.admm(cl.ksp[0], cl.sens[0], phi, m, cfg["lam"], cfg["rho"], 8, 300, 5, cfg["seed"], g=0,
+                 replay=(r0["k_freeze"], r0["outer_iterations"]))
+    assert rel(got[0], ref.alpha) < 1e-4
+    plan.close()
+
+
 def test_nonfinite_host_input_rejected():
     phi, sens, masks, ksp = random_problem(4, 32, 32, 2, 4, 2, S=1)
     plan = _plan(phi, [dict(ny=32, nz=32, ncoils=2, nslices=1, masks=masks)], lam=0.01, rho=0.1)

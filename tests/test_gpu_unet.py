@@ -76,6 +76,14 @@ def test_forward_matches_oracle():
         c = cos(got_net.ravel(), ref_net.ravel())
         _say(f"  slice {s}: net(x) rel L2 {e:.3e} cosine {c:.6f}")
         assert e < 2e-2 and c > 0.999
+    # an all-zero slice (no data) maps to an all-zero start; the other slice of the
+    # batch is unchanged
+    d_in[1] = 0
+    d_out2 = torch.empty_like(d_in)
+    net.forward(d_in, d_out2)
+    torch.cuda.synchronize()
+    assert not d_out2[1].any()
+    assert torch.equal(d_out2[0], d_out[0])
     net.close()
 
 
