@@ -175,6 +175,12 @@ int t2s_get_schedule(const t2s_plan* plan, int cls, int* chunk, int* nstreams);
 #define T2S_ORDER_XCD_PASS_A 1
 #define T2S_ORDER_XCD_PASS_C 2
 int t2s_set_order(t2s_plan* plan, int cls, int order);
+
+/* Global index of class `cls`'s slice 0 in the block-shift schedule (default: the
+ * number of slices in the classes before it).  Lets a volume be split over several
+ * plans (or devices) with every slice keeping the shifts, and so the result, it has
+ * in one plan.  Errors: T2S_EINVAL. */
+int t2s_set_slice_offset(t2s_plan* plan, int cls, int first_global);
 int t2s_get_order(const t2s_plan* plan, int cls, int* order);
 
 /* Pick every class's schedule by timing `reps` CG steps of passes A/B/C per

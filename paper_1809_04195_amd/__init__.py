@@ -123,6 +123,7 @@ _SIGS = {
                          ctypes.c_int),
     "t2s_autotune": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "t2s_set_order": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "t2s_set_slice_offset": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "t2s_get_order": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "t2s_unet_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                          ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
@@ -315,6 +316,10 @@ def t2s_get_schedule(plan, cls):
 
 def t2s_set_order(plan, cls, order):
     return _check(lib().t2s_set_order(plan, cls, order))
+
+
+def t2s_set_slice_offset(plan, cls, first_global):
+    return _check(lib().t2s_set_slice_offset(plan, cls, first_global))
 
 
 def t2s_get_order(plan, cls):

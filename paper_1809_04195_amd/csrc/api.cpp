@@ -337,7 +337,8 @@ int run_outer_all(t2s_plan* plan, int mode, hipStream_t st) {
 std::string sched_signature(const t2s_plan* plan, int mode) {
     std::string k = std::to_string(mode);
     for (const ClassPlan& c : plan->cls)
-        k += "/" + std::to_string(c.chunk) + "x" + std::to_string(c.nstreams) + "o" + std::to_string(c.order);
+        k += "/" + std::to_string(c.chunk) + "x" + std::to_string(c.nstreams) + "o" + std::to_string(c.order) + "g" +
+             std::to_string(c.gbase);
     return k;
 }
 
@@ -835,6 +836,15 @@ int t2s_set_order(t2s_plan* plan, int cls, int order) {
     if (order & ~(T2S_ORDER_XCD_PASS_A | T2S_ORDER_XCD_PASS_C)) return fail(T2S_EINVAL, "unknown order flags");
     plan->cls[cls].order = order;
     plan->cls[cls].args.order = order;
+    return 0;
+}
+
+int t2s_set_slice_offset(t2s_plan* plan, int cls, int first_global) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
+    if (first_global < 0) return fail(T2S_EINVAL, "first_global must be >= 0");
+    plan->cls[cls].gbase = first_global;
+    plan->cls[cls].args.gbase = first_global;
     return 0;
 }
 

@@ -21,7 +21,7 @@ import time
 import numpy as np
 
 from . import (T2S_ADJOINT, T2S_ALPHA, T2S_BATCHED, T2S_BATCHED_GRAPH, T2S_PER_SLICE, Plan, UNet, t2s_autotune,
-               t2s_get_order, t2s_get_schedule)
+               t2s_get_order, t2s_get_schedule, t2s_set_slice_offset)
 from .traffic_model import bytes_per_outer
 
 
@@ -116,45 +116,77 @@ def train(net, b0, alpha, epochs, batch, lr, seed):
 # ---------------------------------------------------------------------------
 
 
-def run_tolerance(phi, cl, cfg, start, net=None, batch=16, mode=T2S_BATCHED_GRAPH):
-    """Load, optionally warm start, reconstruct to tol.  start: 'cold' | 'b0' | 'net';
-    mode: T2S_BATCHED_GRAPH (batched) or T2S_PER_SLICE (one launch sequence per slice)."""
+def _solve_group(phi, cl, cfg, start, net, batch, mode, first, count, tune):
+    """Reconstruct slices [first, first + count) of the volume to tol in one plan whose
+    slice 0 has global index `first` (same shifts as in a whole-volume plan).
+    Returns (wall seconds of load + start + solve, reports, alpha, alpha0, schedule, order)."""
     import torch
-    S = cl.nslices
-    plan = Plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=S, masks=cl.masks)], lam=cfg["lam"],
+    sl = slice(first, first + count)
+    plan = Plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=count, masks=cl.masks)], lam=cfg["lam"],
                 rho=cfg["rho"], block=cfg["block"], n_outer=cfg["n_outer"], n_cg=cfg["n_cg"], tol=cfg["tol"],
                 seed=cfg["seed"], freeze_window=5, freeze_stall=0.05, check_every=5)
-    dsens = torch.from_numpy(np.ascontiguousarray(cl.sens)).cuda()
-    dksp = torch.from_numpy(np.ascontiguousarray(cl.ksp)).cuda()
-    plan.load(0, 0, dsens, dksp)
-    t2s_autotune(plan.handle, 2)
+    t2s_set_slice_offset(plan.handle, 0, first)
+    dsens = torch.from_numpy(np.ascontiguousarray(cl.sens[sl])).cuda()
+    dksp = torch.from_numpy(np.ascontiguousarray(cl.ksp[sl])).cuda()
+    if tune:
+        plan.load(0, 0, dsens, dksp)
+        t2s_autotune(plan.handle, 2)
     sched, order = t2s_get_schedule(plan.handle, 0), t2s_get_order(plan.handle, 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.load(0, 0, dsens, dksp)
     a0 = None
     if start != "cold":
-        b0 = plan.read(0, 0, S, T2S_ADJOINT, device=True)
+        b0 = plan.read(0, 0, count, T2S_ADJOINT, device=True)
         if start == "b0":
             a0 = b0
         else:
             a0 = torch.empty_like(b0)
-            for i in range(0, S, batch):
+            for i in range(0, count, batch):
                 net.forward(b0[i:i + batch], a0[i:i + batch])
         plan.set_initial(0, 0, a0)
     code = plan.reconstruct(mode)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    reps = [plan.report(0, s) for s in range(S)]
-    alpha = plan.read(0, 0, S, T2S_ALPHA, device=True)
+    reps = [plan.report(0, s) for s in range(count)]
+    alpha = plan.read(0, 0, count, T2S_ALPHA, device=True)
     plan.close()
+    return wall, reps, alpha, a0, sched, order, code
+
+
+def run_tolerance(phi, cl, cfg, start, net=None, batch=16, mode=T2S_BATCHED_GRAPH, group=0):
+    """Load, optionally warm start, reconstruct to tol.  start: 'cold' | 'b0' | 'net';
+    mode: T2S_BATCHED_GRAPH (batched, autotuned) or T2S_PER_SLICE (one launch sequence
+    per slice).  `group` > 0 runs the volume as consecutive plans of that many slices
+    (each slice keeps its global index, so the arithmetic is unchanged) and reports the
+    summed time; it is meant for the per-slice schedule, which gains nothing from
+    having the whole volume in one plan."""
+    import torch
+    S = cl.nslices
+    group = group or S
+    wall, reps, alphas, a0s, code = 0.0, [], [], [], 0
+    for first in range(0, S, group):
+        n = min(group, S - first)
+        w, r, a, a0, sched, order, c = _solve_group(phi, cl, cfg, start, net, batch, mode, first, n,
+                                                    tune=mode != T2S_PER_SLICE)
+        wall += w
+        reps += r
+        alphas.append(a)
+        a0s.append(a0)
+        code = max(code, int(c))
+        if group < S:
+            log(f"  {start} ({'per-slice' if mode == T2S_PER_SLICE else 'batched'}): slices {first}..{first + n - 1} "
+                f"in {w:.1f} s")
+    alpha = torch.cat(alphas)
+    a0 = None if a0s[0] is None else torch.cat(a0s)
     its = np.array([r["outer_iterations"] for r in reps])
     alg = float(its.sum()) * bytes_per_outer(cl.ny, cl.nz, cl.ncoils, phi.shape[1], cfg["n_cg"])
     res = dict(start=start, mode="per_slice" if mode == T2S_PER_SLICE else "batched_graph", s_per_volume=wall,
                slices_per_s=S / wall, outer_mean=float(its.mean()), outer_max=int(its.max()), outer_min=int(its.min()),
                converged=int(sum(r["converged"] for r in reps)), slices=S, code=int(code),
                final_residual_max=float(max(max(r["r_primal"], r["r_dual"]) for r in reps)),
-               solver_alg_gbs=alg / wall / 1e9, schedule=list(sched), order=order)
+               solver_alg_gbs=alg / wall / 1e9, schedule=list(sched), order=order,
+               plans=(S + group - 1) // group)
     return res, alpha, a0
 
 
@@ -183,6 +215,8 @@ def main():
     ap.add_argument("--params", type=str, default="", help="trained parameters (.npy): skip data generation and training")
     ap.add_argument("--train-only", action="store_true", help="stop after training (parameters saved)")
     ap.add_argument("--plain", action="store_true", help="also run the plain solver: per-slice launches, cold start")
+    ap.add_argument("--plain-group", type=int, default=32,
+                    help="slices per plan of the plain run (progress is printed per plan)")
     ap.add_argument("--starts", type=str, default="cold,b0,net",
                     help="batched runs to make (comma list of cold, b0, net; empty with --plain: plain only)")
     args = ap.parse_args()
@@ -254,7 +288,7 @@ def main():
         a0n = sols["net"][1]
         out["start_error_vs_solution"] = dict(net=rel(a0n, ref), b0=rel(sols["b0"][1], ref), zero=1.0)
     if args.plain:
-        r, _, _ = run_tolerance(phi, cl, ecfg, "cold", None, mode=T2S_PER_SLICE)
+        r, _, _ = run_tolerance(phi, cl, ecfg, "cold", None, mode=T2S_PER_SLICE, group=args.plain_group)
         runs["plain"] = r
         log(f"plain (per-slice launches, cold): {r}")
         if full:

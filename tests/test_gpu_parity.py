@@ -303,6 +303,22 @@ def test_workgroup_orders_bitwise():
         assert np.array_equal(outs[order], outs[0]), order
 
 
+def test_slice_offset_splits_volume_bitwise():
+    _say("a 4-slice plan vs two 2-slice plans with global slice offsets 0 and 2")
+    phi, sens, masks, ksp = random_problem(35, 64, 64, 3, 8, 3, S=4, frac=0.3)
+    whole = _run_sched(phi, sens, masks, ksp, T.T2S_BATCHED)[0]
+    parts = []
+    for first in (0, 2):
+        plan = _plan(phi, [dict(ny=64, nz=64, ncoils=3, nslices=2, masks=masks)], lam=0.05, rho=0.1, n_outer=4,
+                     n_cg=3, seed=17)
+        T.t2s_set_slice_offset(plan.handle, 0, first)
+        plan.load(0, 0, sens[first:first + 2], ksp[first:first + 2])
+        plan.reconstruct(T.T2S_PER_SLICE)
+        parts.append(plan.read(0, 0, 2))
+        plan.close()
+    assert np.array_equal(np.concatenate(parts), whole)
+
+
 def test_graph_replay_matches_eager():
     import torch
     _say("hipGraph replay of the outer iteration vs eager launches, 3 replays with eager work between")
