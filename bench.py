@@ -32,6 +32,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on the host cores, one slice per process
+# ---------------------------------------------------------------------------
+
+_CPU = {}
+
+
 def _oracle_job(i):
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import t2s as O
