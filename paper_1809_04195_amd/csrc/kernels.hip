@@ -76,11 +76,13 @@ __device__ __forceinline__ double block_sum_ragged(double v, double* sh) {
     return r;
 }
 
-// Workgroup coordinates.  The dispatcher deals linear workgroup ids round-robin over
-// the 8 XCDs (each with its own L2); with `grouped`, id i is given the work item
-// (i mod 8) * (total / 8) + i / 8 (when 8 divides the total), so each XCD works
-// through a contiguous run of row tiles.  Which order streams better depends on the
-// shape, so it is a per-class schedule choice.
+// Workgroup coordinates (x = row tile, y = coefficient k, z = slice).  The
+// dispatcher deals linear workgroup ids round-robin over the 8 XCDs (each with its
+// own L2); with `grouped`, id i is given the work item j = (i mod 8) * (total / 8) +
+// i / 8 (when 8 divides the total), so each XCD works through a contiguous run of
+// work items, decoded with k fastest: the K workgroups that read the same coil-map
+// rows run back to back on one XCD and share them through its L2.  Which order
+// streams better depends on the shape, so it is a per-class schedule choice.
 struct Blk {
     int x, y, z;
 };
@@ -90,7 +92,7 @@ __device__ __forceinline__ Blk block_coords(bool grouped) {
     if (!grouped || (total & 7) != 0) return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
     int i = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
     i = (i & 7) * (total >> 3) + (i >> 3);
-    return Blk{i % gx, (i / gx) % gy, i / (gx * gy)};
+    return Blk{(i / gy) % gx, i % gy, i / (gx * gy)};
 }
 
 __device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[4 * s] != 0; }

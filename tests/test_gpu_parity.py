@@ -68,6 +68,58 @@ def test_normal_operator_and_adjoint(ny, nz, C, Tn, K):
     plan.close()
 
 
+# every supported FFT length as row length (nz) and as column length (ny), C = 1-2
+LENGTH_SHAPES = [(16, 512), (512, 16), (32, 384), (384, 32), (48, 320), (320, 48), (96, 160), (160, 96),
+                 (128, 192), (192, 128), (256, 64), (64, 256)]
+
+
+@pytest.mark.parametrize("ny,nz", LENGTH_SHAPES)
+def test_normal_operator_every_length(ny, nz):
+    import torch
+    K, C, Tn = 2, 2 if ny * nz <= 16384 else 1, 6
+    _say(f"normal-operator parity ny={ny} nz={nz} C={C} K={K}")
+    phi, sens, masks, ksp = random_problem(ny + 3 * nz, ny, nz, C, Tn, K, S=1, frac=0.3)
+    plan = _plan(phi, [dict(ny=ny, nz=nz, ncoils=C, nslices=1, masks=masks)], lam=0.01, rho=0.1, block=16)
+    plan.load(0, 0, sens, ksp)
+    a = crandn(np.random.default_rng(ny * nz), 1, K, ny, nz)
+    a_d = torch.from_numpy(a).cuda()
+    out = torch.empty_like(a_d)
+    T.t2s_apply_normal(plan.handle, 0, 0, 1, a_d, out, 0.0)
+    torch.cuda.synchronize()
+    psi = O.space_time_kernel(phi, masks.astype(bool))
+    e = rel(out.cpu().numpy()[0], O.normal_psi(a[0], sens[0], psi))
+    _say(f"  rel L2 {e:.3e}")
+    assert e < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("K", [6, 7, 8])
+def test_normal_operator_and_llr_large_k(K):
+    import torch
+    _say(f"normal operator and LLR prox at K={K} (64x64, C=2)")
+    phi, sens, masks, ksp = random_problem(40 + K, 64, 64, 2, 12, K, S=1, frac=0.3)
+    plan = _plan(phi, [dict(ny=64, nz=64, ncoils=2, nslices=1, masks=masks)], lam=0.01, rho=0.1)
+    plan.load(0, 0, sens, ksp)
+    rng = np.random.default_rng(K)
+    a = crandn(rng, 1, K, 64, 64)
+    a_d = torch.from_numpy(a).cuda()
+    out = torch.empty_like(a_d)
+    T.t2s_apply_normal(plan.handle, 0, 0, 1, a_d, out, 0.1)
+    torch.cuda.synchronize()
+    psi = O.space_time_kernel(phi, masks.astype(bool))
+    ref = O.normal_psi(a[0], sens[0], psi) + 0.1 * a[0].astype(np.complex128)
+    assert rel(out.cpu().numpy()[0], ref) < 1e-5
+    base = crandn(rng, 1, 2, 64, 64)
+    v = (np.einsum("sjyz,sjk->skyz", base, crandn(rng, 1, 2, K)) + 0.3 * crandn(rng, 1, K, 64, 64)).astype(np.complex64)
+    vd = torch.from_numpy(v).cuda()
+    T.t2s_apply_llr(plan.handle, 0, 0, 1, vd, out, 0.9, [(5, 2)])
+    torch.cuda.synchronize()
+    e = rel(out.cpu().numpy()[0], O.llr_prox(v[0], 0.9, (5, 2), 8))
+    _say(f"  LLR rel L2 {e:.3e}")
+    assert e < 1e-5
+    plan.close()
+
+
 @pytest.mark.parametrize("K,b", [(1, 8), (2, 4), (3, 8), (4, 8), (5, 8), (4, 16), (3, 4)])
 def test_llr_prox(K, b):
     import torch
