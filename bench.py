@@ -81,7 +81,7 @@ def main():
                     help="launch schedule; 'graph' replays a captured outer iteration (no per-kernel events)")
     ap.add_argument("--schedule", type=str, default="0,1",
                     help="'auto' (autotuner), or CHUNK,STREAMS applied to every shape class")
-    ap.add_argument("--order", type=int, default=1,
+    ap.add_argument("--order", type=int, default=0,
                     help="workgroup order flags of passes A / C (1: pass A, 2: pass C grouped by XCD); "
                          "ignored with --schedule auto, which tunes it")
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(16, cores))")

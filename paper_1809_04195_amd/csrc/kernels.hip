@@ -4,9 +4,9 @@
 // normaleq; fused three-pass schedule after Alg. 1):
 //   pass A  (Alg. 1, first panel loop):  per (slice, 16-row tile, k): p = r + beta p
 //           (CG direction update, fused), then for every coil c: S_c p_k and an
-//           nz-point FFT of each row; written transposed ([nz][ny], y contiguous)
-//           so pass B reads whole columns -- the paper's "leave it transposed"
-//           shortcut of Fig. 3 that saves two of four transposes.
+//           nz-point FFT of each row; written column-major in 16 x 16 tiles
+//           (y fastest) so pass B reads whole columns -- the paper's "leave it
+//           transposed" shortcut of Fig. 3 that saves two of four transposes.
 //   pass B  (second loop, with the forward column FFT before Psi that the
 //           printed loop omits): per (slice, coil, column tile): ny-point FFT of
 //           every column of all K coefficient images, the K x K real symmetric
@@ -94,6 +94,15 @@ __device__ __forceinline__ Blk block_coords(bool grouped) {
     i = (i & 7) * (total >> 3) + (i >> 3);
     return Blk{(i / gy) % gx, i % gy, i / (gx * gy)};
 }
+
+// Pass intermediate layout: each ny x nz k-space image is stored as 16 x 16 tiles
+// (2 KiB), tile (y / 16, z / 16) at ((z / 16) (ny / 16) + y / 16) * 256, inside a tile
+// y fastest.  A 16-row tile of a row pass and a 16-column tile of pass B are then
+// whole 2 KiB tiles, and a wave's access is one 512-byte run in every pass (with a
+// plain [z][y] image the row passes touch 128-byte pieces of 2 KiB columns).
+__device__ __forceinline__ size_t tile_col(int z, int ny) { return (size_t)(z >> 4) * (ny >> 4) * 256 + ((z & 15) << 4); }
+__device__ __forceinline__ int tile_row(int y) { return ((y >> 4) << 8) + (y & 15); }
+__device__ __forceinline__ size_t tix(int y, int z, int ny) { return tile_col(z, ny) + tile_row(y); }
 
 __device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[4 * s] != 0; }
 
@@ -186,9 +195,9 @@ __device__ __forceinline__ double cg_row_update(const float2 (&acc)[R1], const f
 
 // ---------------------------------------------------------------------------
 // pass A: per (row tile, k): p = r + beta p, then per coil S_c p_k and the row FFT
-// (register two-step plan), stored transposed.  Two thread mappings meet at the
-// LDS exchange: row-major lanes for the coalesced row loads, row-fastest lanes for
-// the coalesced transposed stores.
+// (register two-step plan), stored column-major in 16 x 16 tiles.  Two thread
+// mappings meet at the LDS exchange: row-major lanes for the coalesced row loads,
+// row-fastest lanes for the stores (a wave writes one 512-byte run of a tile).
 // ---------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_eu(1, passA_waves<L>())))
@@ -256,9 +265,9 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
 #pragma unroll
             for (int n2 = 0; n2 < R2; ++n2) b[n2] = xr3[t3 * (R2 + 1) + n2];
             dft_dir<R2, false>(b);
-            float2* out = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + y0 + r3;
+            float2* out = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + tile_row(y0 + r3);
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) out[(size_t)(t3 + R1 * k2) * ny] = b[k2];
+            for (int k2 = 0; k2 < R2; ++k2) out[tile_col(t3 + R1 * k2, ny)] = b[k2];
         }
         __syncthreads();
     }
@@ -294,14 +303,17 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
     __syncthreads();
     // columns past nz (last tile) read column 0 and are never stored: no selects between
     // the loads and their first use, so the next coefficient's loads stay in flight
-    float2* col = a.tmp + ((size_t)s * a.C + c) * (size_t)K * N + (size_t)(colok ? z : 0) * L;
+    // this thread's first element: column z, row t (t < 16); row R2 n1 + t of the column
+    // is then a compile-time offset tile_row(R2 n1) away (R2 divides 16)
+    static_assert(16 % R2 == 0, "tile rows: R2 must divide 16");
+    float2* col = a.tmp + ((size_t)s * a.C + c) * (size_t)K * N + tile_col(colok ? z : 0, L) + t;
     float2* xw = xb + w * TB;
 
     float2 F[K][R2];
     float2 nxt[R1];   // next coefficient's column, loaded while the current one is transformed
     if (t < R2) {
 #pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) nxt[n1] = col[R2 * n1 + t];
+        for (int n1 = 0; n1 < R1; ++n1) nxt[n1] = col[tile_row(R2 * n1)];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -312,7 +324,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
             if (k + 1 < K) {
 #pragma unroll
                 for (int n1 = 0; n1 < R1; ++n1)
-                    nxt[n1] = col[(size_t)(k + 1) * N + R2 * n1 + t];
+                    nxt[n1] = col[(size_t)(k + 1) * N + tile_row(R2 * n1)];
             }
             dft_dir<R1, false>(v);
 #pragma unroll
@@ -385,7 +397,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
             dft_dir<R1, true>(v);
             if (colok) {
 #pragma unroll
-                for (int m2 = 0; m2 < R1; ++m2) col[(size_t)k * N + t + R2 * m2] = v[m2];
+                for (int m2 = 0; m2 < R1; ++m2) col[(size_t)k * N + tile_row(R2 * m2)] = v[m2];
             }
         }
         __syncthreads();
@@ -417,14 +429,14 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
     const size_t N = (size_t)L * nz;
     for (int i = tid; i < L; i += NT) tw[i] = a.twy[i];
     __syncthreads();
-    float2* col = a.tmp + ((size_t)s * a.C + c) * (size_t)a.K * N + (size_t)(colok ? z : 0) * L;
+    float2* col = a.tmp + ((size_t)s * a.C + c) * (size_t)a.K * N + tile_col(colok ? z : 0, L);
     float2* xw = xb + w * TB;
     for (int k = 0; k < a.K; ++k) {
         if (t < R1) {
             float2 b[R2];
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2)
-                b[k2] = col[(size_t)k * N + t + R1 * k2];
+                b[k2] = col[(size_t)k * N + tile_row(t + R1 * k2)];
             dft_dir<R2, true>(b);
 #pragma unroll
             for (int m1 = 0; m1 < R2; ++m1) xw[m1 * (R1 + 1) + t] = tw_mul<true>(b[m1], tw, t * m1);
@@ -437,7 +449,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
             dft_dir<R1, true>(v);
             if (colok) {
 #pragma unroll
-                for (int m2 = 0; m2 < R1; ++m2) col[(size_t)k * N + t + R2 * m2] = v[m2];
+                for (int m2 = 0; m2 < R1; ++m2) col[(size_t)k * N + tile_row(t + R2 * m2)] = v[m2];
             }
         }
         __syncthreads();
@@ -445,8 +457,8 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
 }
 
 // ---------------------------------------------------------------------------
-// pass C: per (row tile, k): for every coil, read the transposed spectra (row-
-// fastest lanes), inverse row FFT, conj(S_c) (.) accumulated in registers; then
+// pass C: per (row tile, k): for every coil, read the tiled spectra (row-fastest
+// lanes), inverse row FFT, conj(S_c) (.) accumulated in registers; then
 // out = acc + rho_add p (MODE 0), out = acc (MODE 1), or the CG step (MODE 2):
 // w = acc + rho p, a = gamma / <p, M p>, x += a p, r -= a w, partial <r, r>.
 // ---------------------------------------------------------------------------
@@ -485,12 +497,12 @@ void k_passC(ClassArgs a, int s0, float rho_add,
 #pragma unroll
     for (int i = 0; i < R1; ++i) acc[i] = make_float2(0.f, 0.f);
     // spectra of the next coil are loaded while the current one is transformed
-    const float2* T0 = a.tmp + ((size_t)s * a.C * a.K + k) * N + y0 + r3;
+    const float2* T0 = a.tmp + ((size_t)s * a.C * a.K + k) * N + tile_row(y0 + r3);
     const size_t cstride = (size_t)a.K * N;
     float2 nb[R2];
     if (on3) {
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) nb[k2] = T0[(size_t)(t3 + R1 * k2) * ny];
+        for (int k2 = 0; k2 < R2; ++k2) nb[k2] = T0[tile_col(t3 + R1 * k2, ny)];
     }
     for (int c = 0; c < a.C; ++c) {
         if (on3) {
@@ -500,7 +512,7 @@ void k_passC(ClassArgs a, int s0, float rho_add,
             if (c + 1 < a.C) {
                 const float2* in = T0 + (size_t)(c + 1) * cstride;
 #pragma unroll
-                for (int k2 = 0; k2 < R2; ++k2) nb[k2] = in[(size_t)(t3 + R1 * k2) * ny];
+                for (int k2 = 0; k2 < R2; ++k2) nb[k2] = in[tile_col(t3 + R1 * k2, ny)];
             }
             dft_dir<R2, true>(b);
 #pragma unroll
@@ -563,8 +575,8 @@ void k_passC(ClassArgs a, int s0, float rho_add,
 }
 
 // ---------------------------------------------------------------------------
-// projection of the samples onto the basis (adjoint input), uncentred and
-// transposed: tmp[c][k][q], q = z' ny + y', value
+// projection of the samples onto the basis (adjoint input), uncentred, in the tiled
+// layout: tmp[c][k] at (y', z') for q = z' ny + y', value
 // (-1)^(y'+z') / sqrt(N) * sum_{samples at the centred location of q} phi[t][k] y_c
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_project(ClassArgs a, int s0) {
@@ -593,7 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_project(ClassArgs a, int s0) {
     }
     const int yp = q % ny, zp = q / ny;
     const float sc = (((yp + zp) & 1) ? -1.0f : 1.0f) / sqrtf((float)N);
-    float2* out = a.tmp + ((size_t)s * a.C + c) * K * (size_t)N + q;
+    float2* out = a.tmp + ((size_t)s * a.C + c) * K * (size_t)N + tix(yp, zp, ny);
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
         if (k < K) out[(size_t)k * N] = cscale(acc[k], sc);

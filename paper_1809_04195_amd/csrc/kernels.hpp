@@ -42,7 +42,8 @@ struct ClassArgs {
     float2* sens;                // [S][C][ny][nz]
     float2* ksp;                 // [S][C][P]
     float2 *b0, *x, *r, *p, *w, *z, *u;   // [S][K][ny][nz]
-    float2* tmp;                 // [S][C][K][nz][ny]  pass intermediate (k-space, transposed)
+    float2* tmp;                 // [S][C][K][nz/16][ny/16][16][16]  pass intermediate (k-space,
+                                 // 16 x 16 tiles, y fastest inside a tile)
     double* pa;                  // [S][nrw]    ||p||^2 partials of pass A
     double* pb;                  // [S][npb]    k-space partials of <p, A^H A p> (pass B)
     double* rr;                  // [S][2][nrw] <r, r> partials of the CG update (pass C)
