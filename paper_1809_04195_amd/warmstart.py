@@ -221,8 +221,9 @@ def main():
                     help="batched runs to make (comma list of cold, b0, net; empty with --plain: plain only)")
     args = ap.parse_args()
     wl = WORKLOADS[args.workload]
-    args.out = args.out or f"gpurun_out/warmstart_{args.workload}.json"
-    args.save_params = args.save_params or f"gpurun_out/unet_params_{args.workload}.npy"
+    args.out = args.out or f"warmstart_out/warmstart_{args.workload}.json"
+    args.save_params = args.save_params or f"warmstart_out/unet_params_{args.workload}.npy"
+    os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
 
     import torch
 
