@@ -347,10 +347,18 @@ template <> struct RegPlan<320> { static constexpr int R1 = 20, R2 = 16; };
 template <> struct RegPlan<384> { static constexpr int R1 = 24, R2 = 16; };
 template <> struct RegPlan<512> { static constexpr int R1 = 32, R2 = 16; };
 
+// Plan of the row passes (A and C), which transform rows of length nz: the same as
+// RegPlan except at 384, where 16 x 24 puts all 24 threads of a row to work in the
+// row-major phase (coil-map loads, accumulation) and holds 16 values per thread
+// there instead of 24.
 template <int L>
+struct RowPlan : RegPlan<L> {};
+template <> struct RowPlan<384> { static constexpr int R1 = 16, R2 = 24; };
+
+template <int L, class Plan = RegPlan<L>>
 struct RegGeom {
-    static constexpr int R1 = RegPlan<L>::R1;
-    static constexpr int R2 = RegPlan<L>::R2;
+    static constexpr int R1 = Plan::R1;
+    static constexpr int R2 = Plan::R2;
     static_assert(R1 * R2 == L, "plan does not factor L");
     static constexpr int P = R1 > R2 ? R1 : R2;              // threads per transform
     static constexpr int S1 = R2 + 1;                         // forward slot stride (k1 rows)

@@ -123,14 +123,16 @@ __device__ __forceinline__ float2 tw_mul(float2 x, const float2* tw, int e) {
 }
 
 template <int L>
-constexpr int rows_threads() { return kRowTile * RegGeom<L>::P; }
+using RowGeom = RegGeom<L, RowPlan<L>>;
+template <int L>
+constexpr int rows_threads() { return kRowTile * RowGeom<L>::P; }
 // Occupancy targets of the row passes.  Left free, the register scheduler trades the
 // batched issue of a coil's loads for one more wave per SIMD and then waits on every
 // load in turn, which costs far more than the extra wave gains.
 // Pass A: three waves while a thread holds at most 16 values per row, else two
 // (24 values per thread at ny = 384 need the larger register budget).
 template <int L>
-constexpr int passA_waves() { return RegGeom<L>::R1 <= 16 ? 3 : 2; }
+constexpr int passA_waves() { return RowGeom<L>::P <= 16 ? 3 : 2; }
 constexpr int kPassCWavesPerSimd = 2;
 
 // p = r (first) or r + beta p on the R1 positions R2 n1 + t of one row: every load is
@@ -205,7 +207,7 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
                                                               int src_s0, int first, PartialSrc gc, PartialSrc gp,
                                                               int want_pp) {
     const Blk bk = block_coords(a.order & kOrderXcdA);
-    using G = RegGeom<L>;
+    using G = RowGeom<L>;
     constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
     static_assert(NT % 64 == 0, "block_sum needs whole waves");
     __shared__ float2 tw[L];
@@ -468,7 +470,7 @@ void k_passC(ClassArgs a, int s0, float rho_add,
                                                               float2* __restrict__ outp, int out_s0, PartialSrc gc,
                                                               int out_buf) {
     const Blk bk = block_coords(a.order & kOrderXcdC);
-    using G = RegGeom<L>;
+    using G = RowGeom<L>;
     constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
     static_assert(NT % 64 == 0, "block_sum needs whole waves");
     __shared__ float2 tw[L];
@@ -894,7 +896,7 @@ bool reg_plan(int L, int* R1, int* R2) {
 }
 
 template <int L>
-static size_t rows_lds() { return (L + kRowTile * RegGeom<L>::TB) * sizeof(float2) + 16 * sizeof(double); }
+static size_t rows_lds() { return (L + kRowTile * RowGeom<L>::TB) * sizeof(float2) + 16 * sizeof(double); }
 template <int L>
 static size_t cols_lds() { return (L + colB<L>() * RegGeom<L>::TB) * sizeof(float2); }
 
