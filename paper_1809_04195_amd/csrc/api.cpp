@@ -404,7 +404,7 @@ void residuals_from_hist(const double* h, double b0_norm, double* rp, double* rd
 
 extern "C" {
 
-int t2s_version(void) { return 101; }
+int t2s_version(void) { return 102; }
 
 const char* t2s_last_error(void) { return g_err.c_str(); }
 
