@@ -133,7 +133,10 @@ constexpr int rows_threads() { return kRowTile * RowGeom<L>::P; }
 // (24 values per thread at ny = 384 need the larger register budget).
 template <int L>
 constexpr int passA_waves() { return RowGeom<L>::P <= 16 ? 3 : 2; }
-constexpr int kPassCWavesPerSimd = 2;
+// Pass C: a three-wave budget (168 registers) still keeps the batched loads of the CG
+// update at ny = 256 and lets the fused update run at three waves per SIMD; larger
+// rows take more registers and run at two.
+constexpr int kPassCWavesPerSimd = 3;
 
 // p = r (first) or r + beta p on the R1 positions R2 n1 + t of one row: every load is
 // issued before the first store (restrict: r and p never overlap), the new p is kept
