@@ -104,6 +104,36 @@ __device__ __forceinline__ size_t tile_col(int z, int ny) { return (size_t)(z >>
 __device__ __forceinline__ int tile_row(int y) { return ((y >> 4) << 8) + (y & 15); }
 __device__ __forceinline__ size_t tix(int y, int z, int ny) { return tile_col(z, ny) + tile_row(y); }
 
+// The pass intermediate is streamed: each pass reads or writes every element once and
+// the next pass finds it in HBM, not in cache (a class's intermediate is gigabytes).
+// Nontemporal loads and stores of it keep the cache for what a class shares (the Psi
+// table, twiddles, partial sums).  NT selects them; plain accesses otherwise.
+typedef float f2vec __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+    if constexpr (NT) {
+        const f2vec r = __builtin_nontemporal_load(reinterpret_cast<const f2vec*>(p));
+        return make_float2(r.x, r.y);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void st_stream(float2* p, float2 v) {
+    if constexpr (NT) {
+        f2vec r;
+        r.x = v.x;
+        r.y = v.y;
+        __builtin_nontemporal_store(r, reinterpret_cast<f2vec*>(p));
+    } else {
+        *p = v;
+    }
+}
+// Pass B at 384 points per column (K = 5, 16 coils) measured 2.5 % slower with
+// nontemporal accesses, at 256 points 6 % faster; passes A and C gain at both sizes.
+template <int L>
+constexpr bool passB_nt() { return L < 384; }
+
 __device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[4 * s] != 0; }
 
 __host__ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
@@ -272,7 +302,7 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
             dft_dir<R2, false>(b);
             float2* out = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + tile_row(y0 + r3);
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) out[tile_col(t3 + R1 * k2, ny)] = b[k2];
+            for (int k2 = 0; k2 < R2; ++k2) st_stream<true>(&out[tile_col(t3 + R1 * k2, ny)], b[k2]);
         }
         __syncthreads();
     }
@@ -318,7 +348,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
     float2 nxt[R1];   // next coefficient's column, loaded while the current one is transformed
     if (t < R2) {
 #pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) nxt[n1] = col[tile_row(R2 * n1)];
+        for (int n1 = 0; n1 < R1; ++n1) nxt[n1] = ld_stream<passB_nt<L>()>(&col[tile_row(R2 * n1)]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -329,7 +359,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
             if (k + 1 < K) {
 #pragma unroll
                 for (int n1 = 0; n1 < R1; ++n1)
-                    nxt[n1] = col[(size_t)(k + 1) * N + tile_row(R2 * n1)];
+                    nxt[n1] = ld_stream<passB_nt<L>()>(&col[(size_t)(k + 1) * N + tile_row(R2 * n1)]);
             }
             dft_dir<R1, false>(v);
 #pragma unroll
@@ -402,7 +432,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
             dft_dir<R1, true>(v);
             if (colok) {
 #pragma unroll
-                for (int m2 = 0; m2 < R1; ++m2) col[(size_t)k * N + tile_row(R2 * m2)] = v[m2];
+                for (int m2 = 0; m2 < R1; ++m2) st_stream<passB_nt<L>()>(&col[(size_t)k * N + tile_row(R2 * m2)], v[m2]);
             }
         }
         __syncthreads();
@@ -507,7 +537,7 @@ void k_passC(ClassArgs a, int s0, float rho_add,
     float2 nb[R2];
     if (on3) {
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) nb[k2] = T0[tile_col(t3 + R1 * k2, ny)];
+        for (int k2 = 0; k2 < R2; ++k2) nb[k2] = ld_stream<true>(&T0[tile_col(t3 + R1 * k2, ny)]);
     }
     for (int c = 0; c < a.C; ++c) {
         if (on3) {
@@ -517,7 +547,7 @@ void k_passC(ClassArgs a, int s0, float rho_add,
             if (c + 1 < a.C) {
                 const float2* in = T0 + (size_t)(c + 1) * cstride;
 #pragma unroll
-                for (int k2 = 0; k2 < R2; ++k2) nb[k2] = in[tile_col(t3 + R1 * k2, ny)];
+                for (int k2 = 0; k2 < R2; ++k2) nb[k2] = ld_stream<true>(&in[tile_col(t3 + R1 * k2, ny)]);
             }
             dft_dir<R2, true>(b);
 #pragma unroll
