@@ -216,6 +216,35 @@ int t2s_apply_normal(t2s_plan* plan, int cls, int first, int count, const void* 
 int t2s_apply_llr(t2s_plan* plan, int cls, int first, int count, const void* in, void* out,
                   float tau, const int* shifts, void* stream);
 
+/* ---- FISTA (the paper's own solver, Sec. II-A and Table 1) ---- */
+
+/* Largest eigenvalue of A^H A for every slice of class `cls` by `iters` power
+ * iterations started from b0 = A^H y (the loaded adjoint): v <- A^H A v / ||v||, and
+ * L[s] = <v, A^H A v> / <v, v> of the last iteration (0 for a slice whose b0 is 0).
+ * L: host double [nslices of the class].  Synchronises `stream`.  Overwrites the
+ * solver's scratch vectors p and w (not alpha, z, u or the loaded data).  Errors:
+ * T2S_EINVAL, T2S_ESTATE (workspace not bound or a slice not loaded), T2S_EHIP. */
+int t2s_lipschitz(t2s_plan* plan, int cls, int iters, double* L, void* stream);
+
+/* n_iter FISTA iterations (proximal gradient with Beck & Teboulle's momentum) on
+ * eq. t2shpics for every slice of every class, from the current alpha (the loaded
+ * start or the result of an earlier call):
+ *     x_(k+1) = prox_{lambda step}( y_k - step (A^H A y_k - A^H y) ),
+ *     y_(k+1) = x_(k+1) + (t_k - 1) / t_(k+1) (x_(k+1) - x_k),
+ * t_0 = 1, t_(k+1) = (1 + sqrt(1 + 4 t_k^2)) / 2, y_0 = x_0 = alpha.  The prox is the
+ * LLR singular-value threshold lambda * step at the block shift of slice g and
+ * iteration k (the same shift schedule as the ADMM z-step, Sec. IV-C).  step must be
+ * <= 1 / L for convergence (t2s_lipschitz).  mode: T2S_BATCHED (all slices of a
+ * class per launch) or T2S_PER_SLICE (same arithmetic, one slice per launch).  The
+ * result is alpha (t2s_read_coeffs T2S_ALPHA); the momentum point y is left in z.
+ * The slice report then gives outer_iterations = n_iter and in r_primal the relative
+ * size of the last step ||x_(k+1) - x_k|| / max(||x_k||, ||x_(k+1)||, 0.01 ||b0||)
+ * (NaN when n_iter exceeds n_outer + 1, the history length); r_dual is 0.  The ADMM
+ * state (z, u, r) is overwritten: load again (or t2s_set_initial) before an ADMM
+ * reconstruct.  Errors: T2S_EINVAL (mode, n_iter < 0, step not finite or <= 0),
+ * T2S_ESTATE, T2S_EHIP. */
+int t2s_fista(t2s_plan* plan, int mode, int n_iter, float step, void* stream);
+
 /* Copy the class's fp32 kernel table (upper triangle, [K(K+1)/2][nz][ny] in
  * uncentred order, scaled by 1/(ny nz)) into host memory `out`. */
 int t2s_get_psi(const t2s_plan* plan, int cls, float* out);

@@ -376,16 +376,39 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
 
 
 # ---------------------------------------------------------------------------
-# FISTA (the paper's solver, Sec. II-A) at a fixed block shift, for cross-checks
+# FISTA (the paper's solver, Sec. II-A), at a fixed block shift or under the random
+# shift schedule of the ADMM z-step
 # ---------------------------------------------------------------------------
 
 
-def fista(samples, sens, phi, masks, lam, b, n_iter, shift, step=None):
+def lipschitz(sens, psi, v0, n_iter):
+    """Largest eigenvalue of A^H A by power iteration from v0: v <- N v / ||v||, and the
+    Rayleigh quotient <v, N v> / <v, v> of the last iterate (0 if v0 = 0)."""
+    v = np.asarray(v0, dtype=np.complex128)
+    L = 0.0
+    nv = None
+    for j in range(n_iter):
+        if j > 0:
+            nrm = np.linalg.norm(v)
+            v = nv / nrm if nrm > 0 else nv * 0.0
+        nv = normal_psi(v, sens, psi)
+        vv = np.vdot(v, v).real
+        L = np.vdot(v, nv).real / vv if vv > 0 else 0.0
+    return L
+
+
+def fista(samples, sens, phi, masks, lam, b, n_iter, shift=None, step=None, seed=None, g=0, alpha0=None):
     """Proximal gradient with Nesterov momentum (Beck & Teboulle 2009) on eq. (t2shpics).
 
-    The gradient is A^H A x - A^H y; the step is 1/L with L the largest eigenvalue of
-    A^H A (estimated by power iteration when not given).
+    The gradient is A^H A x - A^H y and the prox is the blocked LLR threshold
+    lambda * step, at the fixed ``shift`` or, with ``seed``, at block_shift(seed, g, k, b)
+    in iteration k.  The step is 1/L with L the largest eigenvalue of A^H A (power
+    iteration from a random vector when not given).  Momentum: t_0 = 1,
+    t_(k+1) = (1 + sqrt(1 + 4 t_k^2)) / 2, y_(k+1) = x_(k+1) + (t_k - 1)/t_(k+1) (x_(k+1) - x_k),
+    started at y_0 = x_0 = alpha0 (0 when not given).
     """
+    if (shift is None) == (seed is None):
+        raise ValueError("give either a fixed shift or a seed")
     sens = np.asarray(sens, dtype=np.complex128)
     phi = np.asarray(phi, dtype=np.float64)
     K = phi.shape[1]
@@ -393,18 +416,15 @@ def fista(samples, sens, phi, masks, lam, b, n_iter, shift, step=None):
     psi = space_time_kernel(phi, masks)
     aty = adjoint(samples, sens, phi, masks)
     if step is None:
-        v = np.random.default_rng(1).standard_normal((K, Ny, Nz)) + 0j
-        for _ in range(100):
-            v = normal_psi(v, sens, psi)
-            v /= np.linalg.norm(v)
-        L = np.vdot(v, normal_psi(v, sens, psi)).real
-        step = 1.0 / L
-    x = np.zeros((K, Ny, Nz), dtype=np.complex128)
+        v0 = np.random.default_rng(1).standard_normal((K, Ny, Nz)) + 0j
+        step = 1.0 / lipschitz(sens, psi, v0, 101)
+    x = np.zeros((K, Ny, Nz), dtype=np.complex128) if alpha0 is None else np.array(alpha0, dtype=np.complex128)
     yk = x.copy()
     t = 1.0
-    for _ in range(n_iter):
+    for k in range(n_iter):
+        sh = shift if seed is None else block_shift(seed, g, k, b)
         grad = normal_psi(yk, sens, psi) - aty
-        x_new = llr_prox(yk - step * grad, lam * step, shift, b)
+        x_new = llr_prox(yk - step * grad, lam * step, sh, b)
         t_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
         yk = x_new + ((t - 1.0) / t_new) * (x_new - x)
         x, t = x_new, t_new

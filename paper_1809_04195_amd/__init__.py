@@ -115,6 +115,9 @@ _SIGS = {
     "t2s_apply_llr": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                        ctypes.c_float, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p], ctypes.c_int),
     "t2s_get_psi": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "t2s_lipschitz": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
+                      ctypes.c_int),
+    "t2s_fista": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_void_p], ctypes.c_int),
     "t2s_profile_enable": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "t2s_profile_read": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
                          ctypes.c_int),
@@ -332,6 +335,17 @@ def t2s_autotune(plan, reps=3, stream=None):
     return _check(lib().t2s_autotune(plan, reps, _stream(stream)))
 
 
+def t2s_lipschitz(plan, cls, nslices, iters=30, stream=None):
+    out = np.zeros(nslices, dtype=np.float64)
+    _check(lib().t2s_lipschitz(plan, cls, iters, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               _stream(stream)))
+    return out
+
+
+def t2s_fista(plan, mode, n_iter, step, stream=None):
+    return _check(lib().t2s_fista(plan, mode, n_iter, step, _stream(stream)))
+
+
 def t2s_get_psi(plan, cls, K, ny, nz):
     out = np.empty((K * (K + 1) // 2, nz, ny), dtype=np.float32)
     _check(lib().t2s_get_psi(plan, cls, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
@@ -371,6 +385,12 @@ class Plan:
 
     def reconstruct(self, mode=T2S_BATCHED, stream=None):
         return t2s_reconstruct(self.handle, mode, stream)
+
+    def lipschitz(self, cls, iters=30, stream=None):
+        return t2s_lipschitz(self.handle, cls, self.classes[cls]["nslices"], iters, stream)
+
+    def fista(self, n_iter, step, mode=T2S_BATCHED, stream=None):
+        return t2s_fista(self.handle, mode, n_iter, step, stream)
 
     def read(self, cls, first, count, which=T2S_ALPHA, device=False, stream=None):
         c = self.classes[cls]

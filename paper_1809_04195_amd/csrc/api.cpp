@@ -315,7 +315,7 @@ int run_outer(t2s_plan* plan, const ClassArgs& a, int s0, int count, int chunk, 
         if (int e = run_passes(plan, a, s0, count, i, chunk, ns, true, st)) return e;
     {
         TIMED(T2S_KERNEL_LLR);
-        HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrAdmm, 0, nullptr, nullptr, a.tau, 0, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrAdmm, 0, nullptr, nullptr, a.tau, 0, 0, 0.f, st));
     }
     HIP_CHECK_LAUNCH(t2s::launch_llr_finalize(a, s0, count, st));
     return 0;
@@ -404,7 +404,7 @@ void residuals_from_hist(const double* h, double b0_norm, double* rp, double* rd
 
 extern "C" {
 
-int t2s_version(void) { return 102; }
+int t2s_version(void) { return 103; }
 
 const char* t2s_last_error(void) { return g_err.c_str(); }
 
@@ -982,7 +982,7 @@ int t2s_get_slice_report(const t2s_plan* plan, int cls, int slice, t2s_slice_rep
     out->k_freeze = c.k_freeze[slice];
     out->converged = c.converged[slice];
     out->r_primal = out->r_dual = std::numeric_limits<double>::quiet_NaN();
-    if (k > 0) {
+    if (k > 0 && k <= plan->hist_len) {
         double h[8];
         HIP_TRY(hipStreamSynchronize(plan->last_stream));
         HIP_TRY(hipMemcpy(h, c.args.hist + ((size_t)slice * plan->hist_len + (k - 1)) * 8, sizeof(h),
@@ -1026,7 +1026,99 @@ int t2s_apply_llr(t2s_plan* plan, int cls, int first, int count, const void* in,
     hipStream_t st = (hipStream_t)stream;
     for (int i = 0; i < count; ++i)
         HIP_CHECK_LAUNCH(t2s::launch_llr(c.args, first + i, 1, t2s::kLlrProx, 0, (const float2*)in + i * n,
-                                         (float2*)out + i * n, tau, shifts[2 * i], shifts[2 * i + 1], st));
+                                         (float2*)out + i * n, tau, shifts[2 * i], shifts[2 * i + 1], 0.f, st));
+    return 0;
+}
+
+int t2s_lipschitz(t2s_plan* plan, int cls, int iters, double* L, void* stream) {
+    if (int e = check_class_index(plan, cls, 0, 1)) return e;
+    if (!L) return fail(T2S_EINVAL, "L is NULL");
+    if (iters < 1) return fail(T2S_EINVAL, "iters must be >= 1");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    ClassPlan& c = plan->cls[cls];
+    for (int s = 0; s < c.S; ++s)
+        if (!c.loaded[s]) return fail(T2S_ESTATE, "not every slice of the class is loaded");
+    const ClassArgs& a = c.args;
+    const size_t n = (size_t)plan->prm.K * c.ny * c.nz;
+    hipStream_t st = (hipStream_t)stream;
+    g_prof = &plan->prof;
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, 0, c.S, 1, -1, -1, st));
+    HIP_TRY(hipMemcpyAsync(a.w, a.b0, (size_t)c.S * n * 8, hipMemcpyDeviceToDevice, st));
+    const PartialSrc none{nullptr, 0, 0};
+    for (int j = 0; j < iters; ++j) {
+        // v <- A^H A v with ||v||^2 (pass A partials) and <v, A^H A v> (pass B partials)
+        if (j > 0) HIP_CHECK_LAUNCH(t2s::launch_normalize(a, 0, c.S, a.w, st));
+        {
+            TIMED(T2S_KERNEL_PASS_A);
+            HIP_CHECK_LAUNCH(t2s::launch_passA(a, 0, c.S, a.w, 0, 1, none, none, 1, st));
+        }
+        {
+            TIMED(T2S_KERNEL_PASS_B);
+            HIP_CHECK_LAUNCH(t2s::launch_passB(a, 0, c.S, 0, 1, st));
+        }
+        {
+            TIMED(T2S_KERNEL_PASS_C);
+            HIP_CHECK_LAUNCH(t2s::launch_passC(a, 0, c.S, 0, 0.f, a.w, 0, st));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<double> pa((size_t)c.S * c.nrw), pb((size_t)c.S * c.npb);
+    HIP_TRY(hipMemcpy(pa.data(), a.pa, pa.size() * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pb.data(), a.pb, pb.size() * 8, hipMemcpyDeviceToHost));
+    for (int s = 0; s < c.S; ++s) {
+        double vv = 0.0, vnv = 0.0;
+        for (int i = 0; i < c.nrw; ++i) vv += pa[(size_t)s * c.nrw + i];
+        for (int i = 0; i < c.npb; ++i) vnv += pb[(size_t)s * c.npb + i];
+        L[s] = vv > 0.0 ? vnv / vv : 0.0;
+    }
+    return 0;
+}
+
+int t2s_fista(t2s_plan* plan, int mode, int n_iter, float step, void* stream) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (mode != T2S_BATCHED && mode != T2S_PER_SLICE) return fail(T2S_EINVAL, "mode must be BATCHED or PER_SLICE");
+    if (n_iter < 0) return fail(T2S_EINVAL, "n_iter must be >= 0");
+    if (!finite_f(step) || !(step > 0.f)) return fail(T2S_EINVAL, "step must be finite and > 0");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    for (const ClassPlan& c : plan->cls)
+        for (int s = 0; s < c.S; ++s)
+            if (!c.loaded[s]) return fail(T2S_ESTATE, "not every slice is loaded");
+    hipStream_t st = (hipStream_t)stream;
+    plan->last_stream = st;
+    g_prof = &plan->prof;
+    const float tau = plan->prm.lambda * step;
+    for (ClassPlan& c : plan->cls) {
+        // every slice active, no frozen shift, iteration counter 0; momentum point y = x
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, 0, st));
+        const size_t n = (size_t)plan->prm.K * c.ny * c.nz;
+        HIP_TRY(hipMemcpyAsync(c.args.z, c.args.x, (size_t)c.S * n * 8, hipMemcpyDeviceToDevice, st));
+    }
+    auto step_range = [&](const ClassArgs& a, int s0, int count) -> int {
+        // A^H A y into w (pass C without the rho term), then the fused prox and momentum
+        if (int e = run_normal(a, s0, count, a.z, 0, 0.f, a.w, 0, st)) return e;   // class arrays: slice s at s K N
+        {
+            TIMED(T2S_KERNEL_LLR);
+            HIP_CHECK_LAUNCH(t2s::launch_llr(a, s0, count, t2s::kLlrFista, 0, nullptr, nullptr, tau, 0, 0, step, st));
+        }
+        HIP_CHECK_LAUNCH(t2s::launch_llr_finalize(a, s0, count, st));
+        return 0;
+    };
+    for (int it = 0; it < n_iter; ++it) {
+        for (ClassPlan& c : plan->cls) {
+            if (mode == T2S_PER_SLICE) {
+                for (int s = 0; s < c.S; ++s)
+                    if (int e = step_range(c.args, s, 1)) return e;
+            } else if (int e = step_range(c.args, 0, c.S)) {
+                return e;
+            }
+        }
+    }
+    for (ClassPlan& c : plan->cls) {
+        std::fill(c.outer_run.begin(), c.outer_run.end(), n_iter);
+        std::fill(c.k_freeze.begin(), c.k_freeze.end(), -1);
+        std::fill(c.converged.begin(), c.converged.end(), 0);
+    }
+    plan->reconstructed = true;
     return 0;
 }
 

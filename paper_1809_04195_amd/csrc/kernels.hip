@@ -26,6 +26,7 @@
 // Gram matrix per block by cross-lane sums, complex Jacobi eigen-decomposition in
 // FP64, W = V diag(max(sigma - tau, 0) / sigma) V^H, z = v W, fused with the ADMM
 // u- and residual updates.
+#include <algorithm>
 #include <cmath>
 
 #include "fft.hpp"
@@ -740,12 +741,26 @@ __device__ __forceinline__ void jacobi_eig(cd2 (&A)[K][K], cd2 (&V)[K][K]) {
     }
 }
 
+// FISTA point of one voxel and coefficient: the gradient step y - step (A^H A y - b0)
+// from the momentum point y (held in z), A^H A y (in w) and b0 = A^H y_data
+__device__ __forceinline__ float2 fista_point(const ClassArgs& a, size_t i, float step) {
+    const float2 y = a.z[i], g = csub(a.w[i], a.b0[i]);
+    return make_float2(y.x - step * g.x, y.y - step * g.y);
+}
+
+// MODE kLlrAdmm: z = SVT(x + u) with the ADMM u and right-hand-side updates.
+// MODE kLlrProx: out = SVT(in) at an explicit shift.
+// MODE kLlrFista: x_new = SVT(y - step (A^H A y - b0)), the next momentum point
+// y = x_new + (t_k - 1) / t_(k+1) (x_new - x) into z (Beck & Teboulle's momentum
+// sequence t_0 = 1, t_(k+1) = (1 + sqrt(1 + 4 t_k^2)) / 2, from the iteration counter).
 template <int K, int B, int MODE>
 __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int kouter, const float2* __restrict__ inp,
-                                                   float2* __restrict__ outp, float tau, int sy_arg, int sz_arg) {
+                                                   float2* __restrict__ outp, float tau, int sy_arg, int sz_arg,
+                                                   float step) {
     __shared__ double red[kThreads / 64];
+    constexpr bool kState = MODE == kLlrAdmm || MODE == kLlrFista;   // class vectors, device counter
     const int s = s0 + blockIdx.z;
-    if (MODE == kLlrAdmm && !slice_active(a, s)) return;
+    if (kState && !slice_active(a, s)) return;
     const int ny = a.ny, nz = a.nz;
     const size_t N = (size_t)ny * nz;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -754,7 +769,7 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
     const int st = blockIdx.x * (kThreads / 64) + wave;
 
     int sy = sy_arg, sz = sz_arg;
-    if (MODE == kLlrAdmm) {
+    if (kState) {
         // outer index from the device counter (so an outer iteration can be replayed
         // from a captured graph); a frozen shift overrides it
         const int fk = a.state[4 * s + 1];
@@ -763,7 +778,14 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
         sy = (int)((h & 0xFFFFFFFFull) % (uint64_t)B);
         sz = (int)((h >> 32) % (uint64_t)B);
     }
-    const size_t vb = (size_t)(MODE == kLlrAdmm ? s : s - s0) * K * N;
+    const size_t vb = (size_t)(kState ? s : s - s0) * K * N;
+    float mom = 0.0f;
+    if (MODE == kLlrFista) {
+        const int kk = a.state[4 * s + 2];
+        double t = 1.0;
+        for (int j = 0; j < kk; ++j) t = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        mom = (float)((t - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t))));
+    }
     const bool valid = st < nstrips;
     const int prow = valid ? st / nsz : 0;
     const int col = (valid ? (st % nsz) : 0) * 64 + lane;
@@ -784,6 +806,7 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (MODE == kLlrAdmm) v[k] = cadd(a.x[vb + k * N + idx], a.u[vb + k * N + idx]);
+                else if (MODE == kLlrFista) v[k] = fista_point(a, vb + k * N + idx, step);
                 else v[k] = inp[vb + k * N + idx];
             }
 #pragma unroll
@@ -849,6 +872,9 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
                     xv[k] = a.x[idx + k * N];
                     uv[k] = a.u[idx + k * N];
                     v[k] = cadd(xv[k], uv[k]);
+                } else if (MODE == kLlrFista) {
+                    xv[k] = a.x[idx + k * N];
+                    v[k] = fista_point(a, idx + k * N, step);
                 } else {
                     v[k] = inp[idx + k * N];
                 }
@@ -875,13 +901,21 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
                     s_z += (double)zl.x * zl.x + (double)zl.y * zl.y;
                     s_u += (double)un.x * un.x + (double)un.y * un.y;
                     s_r += (double)rn.x * rn.x + (double)rn.y * rn.y;
+                } else if (MODE == kLlrFista) {
+                    const float2 dx = csub(zl, xv[l]);
+                    a.x[idx + l * N] = zl;
+                    a.z[idx + l * N] = make_float2(zl.x + mom * dx.x, zl.y + mom * dx.y);
+                    s_az += (double)dx.x * dx.x + (double)dx.y * dx.y;
+                    s_a += (double)xv[l].x * xv[l].x + (double)xv[l].y * xv[l].y;
+                    s_z += (double)zl.x * zl.x + (double)zl.y * zl.y;
                 } else {
                     outp[idx + l * N] = zl;
                 }
             }
         }
     }
-    if (MODE == kLlrAdmm) {
+    if (kState) {
+        // FISTA: slot 0 ||x_new - x||^2, 2 ||x||^2, 3 ||x_new||^2 (1, 4, 5 stay 0)
         double sums[6] = {s_az, s_zz, s_a, s_z, s_u, s_r};
         double* dst = a.llr + ((size_t)s * a.nllr + blockIdx.x) * 8;
 #pragma unroll
@@ -889,7 +923,7 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
             const double t = block_sum(sums[j], red);
             if (threadIdx.x == 0) {
                 dst[j] = t;
-                if (j == 5) a.g0[(size_t)s * a.nllr + blockIdx.x] = t;
+                if (MODE == kLlrAdmm && j == 5) a.g0[(size_t)s * a.nllr + blockIdx.x] = t;
             }
         }
     }
@@ -1065,39 +1099,65 @@ hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alph
 
 template <int K, int B>
 static void launch_llr_kb(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
-                          float tau, int sy, int sz, hipStream_t st) {
+                          float tau, int sy, int sz, float step, hipStream_t st) {
     const dim3 grid(a.nllr, 1, count);
     if (mode == kLlrAdmm)
-        hipLaunchKernelGGL((k_llr<K, B, kLlrAdmm>), grid, dim3(kThreads), 0, st, a, s0, k, in, out, tau, sy, sz);
+        hipLaunchKernelGGL((k_llr<K, B, kLlrAdmm>), grid, dim3(kThreads), 0, st, a, s0, k, in, out, tau, sy, sz, step);
+    else if (mode == kLlrFista)
+        hipLaunchKernelGGL((k_llr<K, B, kLlrFista>), grid, dim3(kThreads), 0, st, a, s0, k, in, out, tau, sy, sz,
+                           step);
     else
-        hipLaunchKernelGGL((k_llr<K, B, kLlrProx>), grid, dim3(kThreads), 0, st, a, s0, k, in, out, tau, sy, sz);
+        hipLaunchKernelGGL((k_llr<K, B, kLlrProx>), grid, dim3(kThreads), 0, st, a, s0, k, in, out, tau, sy, sz, step);
 }
 
 template <int B>
 static hipError_t launch_llr_b(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in,
-                               float2* out, float tau, int sy, int sz, hipStream_t st) {
+                               float2* out, float tau, int sy, int sz, float step, hipStream_t st) {
     switch (a.K) {
-        case 1: launch_llr_kb<1, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
-        case 2: launch_llr_kb<2, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
-        case 3: launch_llr_kb<3, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
-        case 4: launch_llr_kb<4, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
-        case 5: launch_llr_kb<5, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
-        case 6: launch_llr_kb<6, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
-        case 7: launch_llr_kb<7, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
-        case 8: launch_llr_kb<8, B>(a, s0, count, mode, k, in, out, tau, sy, sz, st); break;
+        case 1: launch_llr_kb<1, B>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st); break;
+        case 2: launch_llr_kb<2, B>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st); break;
+        case 3: launch_llr_kb<3, B>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st); break;
+        case 4: launch_llr_kb<4, B>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st); break;
+        case 5: launch_llr_kb<5, B>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st); break;
+        case 6: launch_llr_kb<6, B>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st); break;
+        case 7: launch_llr_kb<7, B>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st); break;
+        case 8: launch_llr_kb<8, B>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
-                      float tau, int sy, int sz, hipStream_t st) {
+                      float tau, int sy, int sz, float step, hipStream_t st) {
     switch (a.block) {
-        case 4: return launch_llr_b<4>(a, s0, count, mode, k, in, out, tau, sy, sz, st);
-        case 8: return launch_llr_b<8>(a, s0, count, mode, k, in, out, tau, sy, sz, st);
-        case 16: return launch_llr_b<16>(a, s0, count, mode, k, in, out, tau, sy, sz, st);
+        case 4: return launch_llr_b<4>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st);
+        case 8: return launch_llr_b<8>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st);
+        case 16: return launch_llr_b<16>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// v[s] /= ||p[s]|| with ||p||^2 from the pass-A partials (0 when the norm is 0): the
+// renormalisation of the power iteration for the largest eigenvalue of A^H A
+__global__ __launch_bounds__(kThreads) void k_normalize(ClassArgs a, int s0, float2* v) {
+    __shared__ float fac;
+    const int s = s0 + blockIdx.y;
+    if (threadIdx.x == 0) {
+        const double nn = partial_sum(PartialSrc{a.pa, a.nrw, a.nrw}, s);
+        fac = nn > 0.0 ? (float)(1.0 / sqrt(nn)) : 0.0f;
+    }
+    __syncthreads();
+    const size_t n = (size_t)a.K * a.ny * a.nz;
+    float2* vs = v + (size_t)s * n;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads)
+        vs[i] = make_float2(vs[i].x * fac, vs[i].y * fac);
+}
+
+hipError_t launch_normalize(const ClassArgs& a, int s0, int count, float2* v, hipStream_t st) {
+    const size_t n = (size_t)a.K * a.ny * a.nz;
+    const int gx = (int)std::min<size_t>((n + kThreads - 1) / kThreads, 1024);
+    hipLaunchKernelGGL(k_normalize, dim3(gx, count), dim3(kThreads), 0, st, a, s0, v);
+    return hipGetLastError();
 }
 
 __global__ void k_set_state(ClassArgs a, int s0, int count, int active, int frozen, int kreset) {

@@ -58,7 +58,7 @@ constexpr int kOrderXcdA = 1;
 constexpr int kOrderXcdC = 2;
 
 // LLR kernel flavours
-enum LlrMode { kLlrAdmm = 0, kLlrProx = 1 };
+enum LlrMode { kLlrAdmm = 0, kLlrProx = 1, kLlrFista = 2 };
 
 // ---- launchers (return hipSuccess or the launch error) ----
 // s0/count: slices [s0, s0 + count) of the class.
@@ -86,9 +86,13 @@ hipError_t launch_project(const ClassArgs& a, int s0, int count, hipStream_t st)
 // ||b0||^2 into b0n
 hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alpha0, int sub_w, hipStream_t st);
 // ADMM z/u/r update with the shift of the slice's outer counter (mode kLlrAdmm;
-// k unused), or out = prox(in) at the explicit shift (mode kLlrProx)
+// k unused), out = prox(in) at the explicit shift (mode kLlrProx), or one FISTA step
+// x = prox(z - step (w - b0)), z = x + momentum (x - x_old) with the shift and the
+// momentum of the slice's counter (mode kLlrFista; step used only there)
 hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
-                      float tau, int sy, int sz, hipStream_t st);
+                      float tau, int sy, int sz, float step, hipStream_t st);
+// v[s] /= sqrt(sum of the pass-A partials pa[s]) for slices [s0, s0 + count)
+hipError_t launch_normalize(const ClassArgs& a, int s0, int count, float2* v, hipStream_t st);
 // state[s] = (active, frozen[, counter = kreset if kreset >= 0]) for slices [s0, s0 + count)
 hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, int kreset,
                             hipStream_t st);

@@ -339,6 +339,63 @@ def test_admm_matches_fista_objective_at_fixed_shift():
     assert abs(fa - ff) / abs(ff) < 1e-8
 
 
+# --- FISTA (the paper's solver, Sec. II-A) and its step size --------------------------------
+
+
+def test_lipschitz_closed_form_full_sampling():
+    # full sampling and an orthonormal basis make Psi = I, so A^H A multiplies every
+    # pixel by sum_c |S_c|^2: its largest eigenvalue is the largest such sum
+    rng = np.random.default_rng(23)
+    phi, _, _ = small_problem(rng, ny=16, nz=16)
+    sens = crandn(rng, 3, 16, 16)
+    sens[:, 5, 7] *= 3.0                      # one pixel well above the rest
+    full = np.ones((phi.shape[0], 16, 16), dtype=bool)
+    psi = O.space_time_kernel(phi, full)
+    L = O.lipschitz(sens, psi, crandn(rng, phi.shape[1], 16, 16), 60)
+    assert abs(L - (np.abs(sens) ** 2).sum(0).max()) < 1e-10 * L
+    # zero start vector: no direction to iterate on
+    assert O.lipschitz(sens, psi, np.zeros((phi.shape[1], 16, 16), complex), 3) == 0.0
+
+
+def test_lipschitz_matches_largest_eigenvalue():
+    rng = np.random.default_rng(22)
+    phi, sens, masks = small_problem(rng, ny=8, nz=8, C=2, T=4, K=2, frac=0.5)
+    A = _explicit_matrix(sens, phi, masks)
+    lmax = np.linalg.eigvalsh(A.conj().T @ A)[-1]
+    L = O.lipschitz(sens, O.space_time_kernel(phi, masks), crandn(rng, 2, 8, 8), 4000)
+    assert L <= lmax * (1 + 1e-12) and abs(L - lmax) < 1e-5 * lmax
+
+
+def test_fista_shift_schedule_lambda0_is_min_norm_least_squares():
+    # without the regulariser the shifts do nothing and FISTA from 0 converges to the
+    # minimum-norm least-squares solution of the explicit system
+    rng = np.random.default_rng(22)
+    phi, sens, masks = small_problem(rng, ny=8, nz=8, C=2, T=4, K=2, frac=0.5)
+    A = _explicit_matrix(sens, phi, masks)
+    y = crandn(rng, 2, int(masks.sum()))
+    x_ls = np.linalg.lstsq(A, y.reshape(-1), rcond=None)[0]
+    step = 1.0 / np.linalg.eigvalsh(A.conj().T @ A)[-1]
+    x = O.fista(y, sens, phi, masks, lam=0.0, b=4, n_iter=2000, seed=3, g=1, step=step)
+    assert rel(x.reshape(-1), x_ls) < 1e-10
+
+
+def test_fista_first_step_is_a_prox_gradient_step_at_the_scheduled_shift():
+    # y_0 = x_0 and t_0 = 1 give zero momentum in the first step, so one iteration is
+    # one proximal-gradient step at shift block_shift(seed, g, 0); it differs from the
+    # same step at another shift whenever the threshold bites
+    rng = np.random.default_rng(24)
+    phi, sens, masks = small_problem(rng, ny=16, nz=16, C=2, T=4, K=2, frac=0.4)
+    y = O.forward(crandn(rng, 2, 16, 16), sens, phi, masks)
+    x0 = crandn(rng, 2, 16, 16)
+    seed, g, lam, step = 5, 7, 0.5, 0.9
+    x1 = O.fista(y, sens, phi, masks, lam=lam, b=8, n_iter=1, seed=seed, g=g, step=step, alpha0=x0)
+    grad = O.normal_explicit(x0, sens, phi, masks) - O.adjoint(y, sens, phi, masks)
+    sh = O.block_shift(seed, g, 0, 8)
+    assert rel(x1, O.llr_prox_explicit(x0 - step * grad, lam * step, sh, 8)) < 1e-12
+    other = ((sh[0] + 1) % 8, sh[1])
+    assert rel(x1, O.llr_prox_explicit(x0 - step * grad, lam * step, other, 8)) > 1e-3
+
+
 def test_admm_tolerance_mode_rules():
     # freeze happens only at check points; under random shifts the residual stalls
     # above tol, so the run freezes first and then stops once converged
