@@ -216,6 +216,23 @@ int t2s_apply_normal(t2s_plan* plan, int cls, int first, int count, const void* 
 int t2s_apply_llr(t2s_plan* plan, int cls, int first, int count, const void* in, void* out,
                   float tau, const int* shifts, void* stream);
 
+/* ---- Readout pre-step (Sec. II-A end; Sec. IV-A, PICS reconstruction) ---- */
+
+/* Decouple a 3D Cartesian acquisition into readout slices: the 1D unitary inverse
+ * DFT along the fully sampled readout direction, centred like the 2D transform
+ * (index kx is frequency kx - nx/2, x is position x - nx/2):
+ *     out[x][c][p] = (1/sqrt(nx)) sum_kx in[c][p][kx] exp(+2 pi i (kx - nx/2)(x - nx/2) / nx).
+ * in: device complex64 [ncoils][nsamples][nx], for every coil and every sampled
+ * (echo, y, z) entry in mask order (echo-major, then row-major position inside
+ * mask_t) the nx readout samples; out: device complex64 [nx][ncoils][nsamples],
+ * slice x's samples in the layout t2s_load_slices reads (slices [x0, x0 + count) at
+ * out + x0 * ncoils * nsamples).  Stream-ordered, asynchronous; no plan needed.
+ * nx must be one of the supported FFT lengths (16 ... 512, those of the solver).
+ * nsamples = 0 does nothing (in and out may then be NULL).
+ * Errors: T2S_EINVAL (NULL, in and out overlap), T2S_ESHAPE (nx, ncoils outside
+ * [1, 65535], nsamples < 0), T2S_EHIP. */
+int t2s_readout_ifft(int nx, int ncoils, int nsamples, const void* in, void* out, void* stream);
+
 /* ---- FISTA (the paper's own solver, Sec. II-A and Table 1) ---- */
 
 /* Largest eigenvalue of A^H A for every slice of class `cls` by `iters` power

@@ -376,6 +376,21 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
 
 
 # ---------------------------------------------------------------------------
+# Readout decoupling (Sec. II-A end; Sec. IV-A, before the PICS reconstruction): a
+# 1D unitary inverse DFT along the fully sampled readout turns 3D data into slices
+# ---------------------------------------------------------------------------
+
+
+def readout_ifft(ksp3d):
+    """Centred unitary inverse DFT along the last axis of [C, P, Nx] samples (index kx is
+    frequency kx - Nx/2, output x is position x - Nx/2), returned as [Nx, C, P]: slice x's
+    samples in mask order."""
+    k = np.asarray(ksp3d, dtype=np.complex128)
+    x = np.fft.fftshift(np.fft.ifft(np.fft.ifftshift(k, axes=-1), axis=-1, norm="ortho"), axes=-1)
+    return np.moveaxis(x, -1, 0)
+
+
+# ---------------------------------------------------------------------------
 # FISTA (the paper's solver, Sec. II-A), at a fixed block shift or under the random
 # shift schedule of the ADMM z-step
 # ---------------------------------------------------------------------------

@@ -118,6 +118,8 @@ _SIGS = {
     "t2s_lipschitz": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
                       ctypes.c_int),
     "t2s_fista": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_void_p], ctypes.c_int),
+    "t2s_readout_ifft": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                         ctypes.c_int),
     "t2s_profile_enable": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "t2s_profile_read": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
                          ctypes.c_int),
@@ -344,6 +346,14 @@ def t2s_lipschitz(plan, cls, nslices, iters=30, stream=None):
 
 def t2s_fista(plan, mode, n_iter, step, stream=None):
     return _check(lib().t2s_fista(plan, mode, n_iter, step, _stream(stream)))
+
+
+def t2s_readout_ifft(inp, out, stream=None):
+    """inp: device complex64 [C][P][nx]; out: device complex64 [nx][C][P]."""
+    C, P, nx = inp.shape
+    if tuple(out.shape) != (nx, C, P):
+        raise ValueError(f"out must have shape {(nx, C, P)}")
+    return _check(lib().t2s_readout_ifft(nx, C, P, _ptr(inp), _ptr(out), _stream(stream)))
 
 
 def t2s_get_psi(plan, cls, K, ny, nz):

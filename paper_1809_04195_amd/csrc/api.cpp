@@ -1122,6 +1122,21 @@ int t2s_fista(t2s_plan* plan, int mode, int n_iter, float step, void* stream) {
     return 0;
 }
 
+int t2s_readout_ifft(int nx, int ncoils, int nsamples, const void* in, void* out, void* stream) {
+    if (!t2s::fft_supported(nx)) return fail(T2S_ESHAPE, "unsupported readout length " + std::to_string(nx));
+    if (ncoils < 1 || ncoils > 65535) return fail(T2S_ESHAPE, "ncoils must be in [1, 65535]");
+    if (nsamples < 0) return fail(T2S_ESHAPE, "nsamples must be >= 0");
+    if (nsamples == 0) return 0;   // nothing to transform (empty arrays may come as NULL)
+    if (!in || !out) return fail(T2S_EINVAL, "in or out is NULL");
+    const size_t bytes = (size_t)nx * ncoils * nsamples * 8;
+    const char* a = (const char*)in;
+    const char* b = (const char*)out;
+    if (bytes > 0 && a < b + bytes && b < a + bytes) return fail(T2S_EINVAL, "in and out must not overlap");
+    HIP_CHECK_LAUNCH(t2s::launch_readout_ifft(nx, ncoils, nsamples, (const float2*)in, (float2*)out,
+                                              (hipStream_t)stream));
+    return 0;
+}
+
 int t2s_get_psi(const t2s_plan* plan, int cls, float* out) {
     if (int e = check_class_index(plan, cls, 0, 1)) return e;
     if (!out) return fail(T2S_EINVAL, "out is NULL");

@@ -1137,6 +1137,72 @@ hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// readout pre-step: the 1D unitary inverse DFT along the fully sampled readout that
+// decouples a 3D acquisition into independent slices (Sec. II-A end, Sec. IV-A).
+// in [C][P][L]: per coil and per sampled (echo, y, z) entry in mask order, the L
+// readout samples; out [L][C][P]: slice x, coil, sample (what t2s_load_slices reads).
+// Centred like the 2D transform: index kx is frequency kx - L/2 and x is position
+// x - L/2, so X[x] = (-1)^(x + L/2) L^-1/2 sum_kx (-1)^kx Y[kx] exp(+2 pi i kx x / L).
+// A workgroup transforms `readout_lines` consecutive entries of one coil in LDS.
+// ---------------------------------------------------------------------------
+template <int L>
+constexpr int readout_lines() { return L <= 128 ? 16 : (L <= 256 ? 8 : 4); }
+
+template <int L>
+__global__ __launch_bounds__(kThreads) void k_readout_ifft(const float2* __restrict__ in, float2* __restrict__ out,
+                                                           int C, int P) {
+    constexpr int LT = readout_lines<L>(), LD = lds_ld(L);
+    __shared__ float2 tw[L];
+    __shared__ float2 bufa[LT * LD];
+    __shared__ float2 bufb[LT * LD];
+    const int c = blockIdx.y;
+    const int p0 = blockIdx.x * LT;
+    const int nl = min(LT, P - p0);
+    for (int m = threadIdx.x; m < L; m += kThreads) {
+        double sn, cs;
+        sincospi(-2.0 * m / L, &sn, &cs);
+        tw[m] = make_float2((float)cs, (float)sn);
+    }
+    // the tile of nl lines is one contiguous run of nl L values
+    const float2* src = in + ((size_t)c * P + p0) * L;
+    for (int i = threadIdx.x; i < LT * L; i += kThreads) {
+        const int t = i / L, j = i - t * L;
+        float2 v = make_float2(0.f, 0.f);
+        if (t < nl) v = ld_stream<true>(&src[i]);
+        if (j & 1) v = make_float2(-v.x, -v.y);
+        bufa[t * LD + ph(j)] = v;
+    }
+    __syncthreads();
+    const float2* r = fft_lds<L, true>(bufa, bufb, LT, LD, tw);
+    const float sc = (float)(1.0 / sqrt((double)L));
+    for (int i = threadIdx.x; i < LT * L; i += kThreads) {
+        const int x = i / LT, t = i - x * LT;
+        if (t < nl) {
+            const float2 v = r[t * LD + ph(x)];
+            const float f = ((x + L / 2) & 1) ? -sc : sc;
+            st_stream<true>(&out[((size_t)x * C + c) * P + p0 + t], make_float2(v.x * f, v.y * f));
+        }
+    }
+}
+
+hipError_t launch_readout_ifft(int nx, int C, int P, const float2* in, float2* out, hipStream_t st) {
+    if (P == 0) return hipSuccess;
+    switch (nx) {
+#define X(L)                                                                                                   \
+    case L: {                                                                                                  \
+        const dim3 grid((P + readout_lines<L>() - 1) / readout_lines<L>(), C);                                 \
+        hipLaunchKernelGGL(k_readout_ifft<L>, grid, dim3(kThreads), 0, st, in, out, C, P);                    \
+        break;                                                                                                 \
+    }
+        X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // v[s] /= ||p[s]|| with ||p||^2 from the pass-A partials (0 when the norm is 0): the
 // renormalisation of the power iteration for the largest eigenvalue of A^H A
 __global__ __launch_bounds__(kThreads) void k_normalize(ClassArgs a, int s0, float2* v) {

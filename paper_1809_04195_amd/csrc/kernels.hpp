@@ -91,6 +91,9 @@ hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alph
 // momentum of the slice's counter (mode kLlrFista; step used only there)
 hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
                       float tau, int sy, int sz, float step, hipStream_t st);
+// readout pre-step: out[x][c][p] = centred unitary inverse DFT over kx of in[c][p][kx]
+// (nx a supported FFT length, 0 < C <= 65535, P >= 0; in and out must not overlap)
+hipError_t launch_readout_ifft(int nx, int C, int P, const float2* in, float2* out, hipStream_t st);
 // v[s] /= sqrt(sum of the pass-A partials pa[s]) for slices [s0, s0 + count)
 hipError_t launch_normalize(const ClassArgs& a, int s0, int count, float2* v, hipStream_t st);
 // state[s] = (active, frozen[, counter = kreset if kreset >= 0]) for slices [s0, s0 + count)

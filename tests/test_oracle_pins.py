@@ -55,6 +55,23 @@ def test_fft2c_matches_direct_dft(ny, nz):
     assert rel(O.ifft2c(x)[1], Dy.conj().T @ x[1] @ Dz.conj()) < 1e-12
 
 
+@pytest.mark.parametrize("nx", [4, 6, 16, 20])
+def test_readout_ifft_matches_inverse_dft(nx):
+    # decoupling the readout (Sec. II-A end): inverse of the centred unitary DFT,
+    # against the conjugate transpose of the direct DFT matrix, a brute-force sum and
+    # the forward transform
+    rng = np.random.default_rng(nx)
+    k = crandn(rng, 2, 5, nx)
+    out = O.readout_ifft(k)
+    assert out.shape == (nx, 2, 5)
+    D = dft_matrix(nx)
+    assert rel(out, np.moveaxis(k @ D.conj(), -1, 0)) < 1e-12
+    x, c, p = nx // 2 + 1, 1, 3
+    brute = sum(k[c, p, j] * np.exp(2j * np.pi * (j - nx // 2) * (x - nx // 2) / nx) for j in range(nx)) / np.sqrt(nx)
+    assert abs(out[x, c, p] - brute) < 1e-12 * abs(brute)
+    assert rel(np.moveaxis(out, 0, -1) @ D.T, k) < 1e-12
+
+
 # --- T2: centring by +-1 modulation (FFTmod, Sec. IV-A) and the shifted kernel -------------
 
 
