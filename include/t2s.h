@@ -233,6 +233,27 @@ int t2s_apply_llr(t2s_plan* plan, int cls, int first, int count, const void* in,
  * [1, 65535], nsamples < 0), T2S_EHIP. */
 int t2s_readout_ifft(int nx, int ncoils, int nsamples, const void* in, void* out, void* stream);
 
+/* ---- Post-step (Sec. II-B end, eq. backproj; Sec. IV-A post-processing) ---- */
+
+/* Spatial wavelet soft-threshold of every coefficient image of alpha, in place, for
+ * slices [first, first + count) of class `cls`: orthonormal separable 2D Haar
+ * transform with `levels` (1..4) levels, every detail coefficient c replaced by
+ * c max(1 - thresh / |c|, 0) (the final approximation band is kept), inverse
+ * transform.  ny and nz must be multiples of 16.  Run it after the solver; the
+ * result is read with t2s_read_coeffs (T2S_ALPHA).  Errors: T2S_EINVAL (levels,
+ * thresh not finite or < 0, class or slice range), T2S_ESHAPE, T2S_ESTATE, T2S_EHIP. */
+int t2s_wavelet_denoise(t2s_plan* plan, int cls, int first, int count, int levels, float thresh,
+                        void* stream);
+
+/* Back-projection onto echo times (eq. backproj): out[i][j] = sum_k phi_te[j][k]
+ * alpha_k of slice first + i, for n_te (1..8) echo times whose basis rows phi_te
+ * (host float [n_te][K], copied before the call returns) the caller gives, e.g. rows
+ * of Phi at the desired echoes (the paper's TE 21 / 50 / 90 ms).  out: device
+ * complex64 [count][n_te][ny][nz].  Errors: T2S_EINVAL, T2S_ENONFINITE, T2S_ESTATE,
+ * T2S_EHIP. */
+int t2s_backproject(t2s_plan* plan, int cls, int first, int count, int n_te, const float* phi_te,
+                    void* out, void* stream);
+
 /* ---- FISTA (the paper's own solver, Sec. II-A and Table 1) ---- */
 
 /* Largest eigenvalue of A^H A for every slice of class `cls` by `iters` power

@@ -376,6 +376,54 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
 
 
 # ---------------------------------------------------------------------------
+# Post-step (Sec. II-B end; Sec. IV-A post-processing): spatial wavelet
+# soft-threshold of each coefficient image, then back-projection (eq. backproj)
+# ---------------------------------------------------------------------------
+
+
+def haar2(x):
+    """One level of the orthonormal separable 2D Haar transform over the last two axes:
+    (LL, LH, HL, HH), LH differencing along z, HL along y, each half size."""
+    a, b = x[..., 0::2, 0::2], x[..., 0::2, 1::2]
+    c, d = x[..., 1::2, 0::2], x[..., 1::2, 1::2]
+    return (a + b + c + d) / 2, (a - b + c - d) / 2, (a + b - c - d) / 2, (a - b - c + d) / 2
+
+
+def ihaar2(LL, LH, HL, HH):
+    """Inverse of ``haar2``."""
+    out = np.empty(LL.shape[:-2] + (2 * LL.shape[-2], 2 * LL.shape[-1]), dtype=np.result_type(LL, 1.0))
+    out[..., 0::2, 0::2] = (LL + LH + HL + HH) / 2
+    out[..., 0::2, 1::2] = (LL - LH + HL - HH) / 2
+    out[..., 1::2, 0::2] = (LL + LH - HL - HH) / 2
+    out[..., 1::2, 1::2] = (LL - LH - HL + HH) / 2
+    return out
+
+
+def soft_threshold(c, t):
+    """Complex soft threshold: c max(1 - t / |c|, 0)."""
+    r = np.abs(c)
+    return c * np.where(r > t, 1.0 - t / np.maximum(r, 1e-300), 0.0)
+
+
+def wavelet_denoise(alpha, levels, thresh):
+    """`levels`-level orthonormal 2D Haar transform of every image (last two axes), soft
+    threshold of every detail coefficient, inverse; the coarsest approximation is kept."""
+    x = np.asarray(alpha, dtype=np.complex128)
+    details = []
+    for _ in range(levels):
+        x, lh, hl, hh = haar2(x)
+        details.append(tuple(soft_threshold(d, thresh) for d in (lh, hl, hh)))
+    for lh, hl, hh in reversed(details):
+        x = ihaar2(x, lh, hl, hh)
+    return x
+
+
+def backproject(alpha, phi_te):
+    """Images at chosen echo times, eq. (backproj): x_j = sum_k phi_te[j, k] alpha_k."""
+    return np.tensordot(np.asarray(phi_te, dtype=np.float64), np.asarray(alpha, dtype=np.complex128), axes=(1, 0))
+
+
+# ---------------------------------------------------------------------------
 # Readout decoupling (Sec. II-A end; Sec. IV-A, before the PICS reconstruction): a
 # 1D unitary inverse DFT along the fully sampled readout turns 3D data into slices
 # ---------------------------------------------------------------------------

@@ -118,6 +118,10 @@ _SIGS = {
     "t2s_lipschitz": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
                       ctypes.c_int),
     "t2s_fista": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_void_p], ctypes.c_int),
+    "t2s_wavelet_denoise": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                             ctypes.c_void_p], ctypes.c_int),
+    "t2s_backproject": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                         ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "t2s_readout_ifft": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
                          ctypes.c_int),
     "t2s_profile_enable": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
@@ -348,6 +352,17 @@ def t2s_fista(plan, mode, n_iter, step, stream=None):
     return _check(lib().t2s_fista(plan, mode, n_iter, step, _stream(stream)))
 
 
+def t2s_wavelet_denoise(plan, cls, first, count, levels, thresh, stream=None):
+    return _check(lib().t2s_wavelet_denoise(plan, cls, first, count, levels, thresh, _stream(stream)))
+
+
+def t2s_backproject(plan, cls, first, count, phi_te, out, stream=None):
+    """phi_te: host [n_te][K] basis rows; out: device complex64 [count][n_te][ny][nz]."""
+    ph = np.ascontiguousarray(np.asarray(phi_te, dtype=np.float32))
+    return _check(lib().t2s_backproject(plan, cls, first, count, ph.shape[0],
+                                        ph.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _ptr(out), _stream(stream)))
+
+
 def t2s_readout_ifft(inp, out, stream=None):
     """inp: device complex64 [C][P][nx]; out: device complex64 [nx][C][P]."""
     C, P, nx = inp.shape
@@ -401,6 +416,18 @@ class Plan:
 
     def fista(self, n_iter, step, mode=T2S_BATCHED, stream=None):
         return t2s_fista(self.handle, mode, n_iter, step, stream)
+
+    def wavelet_denoise(self, cls, first, count, levels, thresh, stream=None):
+        return t2s_wavelet_denoise(self.handle, cls, first, count, levels, thresh, stream)
+
+    def backproject(self, cls, first, count, phi_te, stream=None):
+        """Device complex64 [count][n_te][ny][nz] images at the echo times of the rows of phi_te."""
+        import torch
+        ph = np.asarray(phi_te, dtype=np.float32).reshape(-1, self.K)
+        c = self.classes[cls]
+        out = torch.empty((count, ph.shape[0], c["ny"], c["nz"]), dtype=torch.complex64, device="cuda")
+        t2s_backproject(self.handle, cls, first, count, ph, out, stream)
+        return out
 
     def read(self, cls, first, count, which=T2S_ALPHA, device=False, stream=None):
         c = self.classes[cls]

@@ -1137,6 +1137,32 @@ int t2s_readout_ifft(int nx, int ncoils, int nsamples, const void* in, void* out
     return 0;
 }
 
+int t2s_wavelet_denoise(t2s_plan* plan, int cls, int first, int count, int levels, float thresh, void* stream) {
+    if (int e = check_class_index(plan, cls, first, count)) return e;
+    if (levels < 1 || levels > 4) return fail(T2S_EINVAL, "levels must be in [1, 4]");
+    if (!finite_f(thresh) || thresh < 0) return fail(T2S_EINVAL, "thresh must be finite and >= 0");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    const ClassPlan& c = plan->cls[cls];
+    if (c.ny % 16 || c.nz % 16) return fail(T2S_ESHAPE, "ny and nz must be multiples of 16");
+    if (count == 0) return 0;
+    HIP_CHECK_LAUNCH(t2s::launch_haar_denoise(c.args, first, count, levels, thresh, (hipStream_t)stream));
+    return 0;
+}
+
+int t2s_backproject(t2s_plan* plan, int cls, int first, int count, int n_te, const float* phi_te, void* out,
+                    void* stream) {
+    if (int e = check_class_index(plan, cls, first, count)) return e;
+    if (!phi_te || (!out && count > 0)) return fail(T2S_EINVAL, "phi_te or out is NULL");
+    if (n_te < 1 || n_te > t2s::kMaxK) return fail(T2S_EINVAL, "n_te must be in [1, 8]");
+    for (int i = 0; i < n_te * plan->prm.K; ++i)
+        if (!finite_f(phi_te[i])) return fail(T2S_ENONFINITE, "phi_te has NaN/Inf");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    if (count == 0) return 0;
+    HIP_CHECK_LAUNCH(t2s::launch_backproject(plan->cls[cls].args, first, count, n_te, phi_te, (float2*)out,
+                                             (hipStream_t)stream));
+    return 0;
+}
+
 int t2s_get_psi(const t2s_plan* plan, int cls, float* out) {
     if (int e = check_class_index(plan, cls, 0, 1)) return e;
     if (!out) return fail(T2S_EINVAL, "out is NULL");

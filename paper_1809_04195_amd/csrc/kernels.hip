@@ -1205,6 +1205,138 @@ hipError_t launch_readout_ifft(int nx, int C, int P, const float2* in, float2* o
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// post-step (Sec. II-B end; Sec. IV-A post-processing): spatial wavelet
+// soft-threshold of every coefficient image, then back-projection x_t = sum_k
+// phi_tk alpha_k at chosen echo times (eq. backproj).
+// Wavelet: orthonormal separable 2D Haar, `levels` <= 4.  A J-level Haar transform
+// only combines values inside aligned 2^J x 2^J squares, so 16 x 16 tiles are
+// transformed independently.  One 2 x 2 Haar step maps a block (a b; c d) to LL, LH
+// (z detail), HL (y detail), HH; the higher levels run in place on the approximation
+// grid: at stride h the block (y, z), (y, z+h), (y+h, z), (y+h, z+h) becomes LL, LH,
+// HL, HH in the same places.  Every position that is not a final approximation then
+// holds a detail coefficient and is shrunk: c -> c max(1 - thr / |c|, 0).  The
+// inverse levels undo the steps (the step is its own inverse).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void haar_block(float2& a, float2& b, float2& c, float2& d) {
+    const float2 s0 = cadd(a, b), d0 = csub(a, b), s1 = cadd(c, d), d1 = csub(c, d);
+    a = make_float2(0.5f * (s0.x + s1.x), 0.5f * (s0.y + s1.y));
+    b = make_float2(0.5f * (d0.x + d1.x), 0.5f * (d0.y + d1.y));
+    c = make_float2(0.5f * (s0.x - s1.x), 0.5f * (s0.y - s1.y));
+    d = make_float2(0.5f * (d0.x - d1.x), 0.5f * (d0.y - d1.y));
+}
+
+__device__ __forceinline__ float2 shrink(float2 v, float thr) {
+    const float r = sqrtf(v.x * v.x + v.y * v.y);
+    const float f = r > thr ? 1.0f - thr / r : 0.0f;
+    return make_float2(v.x * f, v.y * f);
+}
+
+// Four 16 x 16 tiles per workgroup (consecutive in row-major tile order), 64 threads
+// per tile.  Level 1 runs in registers: each thread owns one 2 x 2 block (two 16-byte
+// row loads); its three details stay in registers and its approximation goes to an
+// 8 x 8 LDS grid per tile, where levels 2..J run with the in-place scheme above.
+constexpr int kHaarTiles = kThreads / 64;
+
+__global__ __launch_bounds__(kThreads) void k_haar_denoise(ClassArgs a, int s0, int levels, float thr) {
+    __shared__ float2 t[kHaarTiles][8][9];
+    const int s = s0 + blockIdx.z;
+    const int k = blockIdx.y;
+    const int w = threadIdx.x / 64, q = threadIdx.x % 64;
+    const int ntz = a.nz / 16, ntiles = (a.ny / 16) * ntz;
+    const int tile = blockIdx.x * kHaarTiles + w;
+    const bool on = tile < ntiles;               // uniform over each wave
+    const int by = q / 8, bz = q % 8;
+    float2* img = a.x + ((size_t)s * a.K + k) * a.ny * a.nz;
+    const size_t g0 = on ? (size_t)((tile / ntz) * 16 + 2 * by) * a.nz + (tile % ntz) * 16 + 2 * bz : 0;
+    float2 v00, v01, v10, v11;
+    if (on) {
+        v00 = img[g0];
+        v01 = img[g0 + 1];
+        v10 = img[g0 + a.nz];
+        v11 = img[g0 + a.nz + 1];
+        haar_block(v00, v01, v10, v11);
+        v01 = shrink(v01, thr);
+        v10 = shrink(v10, thr);
+        v11 = shrink(v11, thr);
+        t[w][by][bz] = v00;
+    }
+    __syncthreads();
+    for (int j = 1, h = 1; j < levels; ++j, h <<= 1) {
+        const int nb = 4 / h;
+        if (on && q < nb * nb) {
+            const int y = (q / nb) * 2 * h, z = (q % nb) * 2 * h;
+            haar_block(t[w][y][z], t[w][y][z + h], t[w][y + h][z], t[w][y + h][z + h]);
+        }
+        __syncthreads();
+    }
+    const int m = (1 << (levels - 1)) - 1;
+    if (on && ((by & m) || (bz & m))) t[w][by][bz] = shrink(t[w][by][bz], thr);
+    __syncthreads();
+    for (int j = levels - 1; j >= 1; --j) {
+        const int h = 1 << (j - 1), nb = 4 / h;
+        if (on && q < nb * nb) {
+            const int y = (q / nb) * 2 * h, z = (q % nb) * 2 * h;
+            haar_block(t[w][y][z], t[w][y][z + h], t[w][y + h][z], t[w][y + h][z + h]);
+        }
+        __syncthreads();
+    }
+    if (on) {
+        v00 = t[w][by][bz];
+        haar_block(v00, v01, v10, v11);
+        img[g0] = v00;
+        img[g0 + 1] = v01;
+        img[g0 + a.nz] = v10;
+        img[g0 + a.nz + 1] = v11;
+    }
+}
+
+hipError_t launch_haar_denoise(const ClassArgs& a, int s0, int count, int levels, float thr, hipStream_t st) {
+    const int ntiles = (a.ny / 16) * (a.nz / 16);
+    const dim3 grid((ntiles + kHaarTiles - 1) / kHaarTiles, a.K, count);
+    hipLaunchKernelGGL(k_haar_denoise, grid, dim3(kThreads), 0, st, a, s0, levels, thr);
+    return hipGetLastError();
+}
+
+// out[s][j][n] = sum_k phi_te[j][k] alpha[s][k][n] for slices [s0, s0 + count)
+// (out holds slices from s0 on); one thread per voxel, all echo times at once
+struct PhiTe {
+    float v[kMaxK * kMaxK];
+};
+__global__ __launch_bounds__(kThreads) void k_backproject(ClassArgs a, int s0, int nte, PhiTe ph, float2* out) {
+    const int s = s0 + blockIdx.y;
+    const size_t N = (size_t)a.ny * a.nz;
+    const int K = a.K;
+    const float2* al = a.x + (size_t)s * K * N;
+    float2* o = out + (size_t)(s - s0) * nte * N;
+    for (size_t n = (size_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += (size_t)gridDim.x * kThreads) {
+        float2 v[kMaxK];
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k) v[k] = k < K ? al[k * N + n] : make_float2(0.f, 0.f);
+        for (int j = 0; j < nte; ++j) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int k = 0; k < kMaxK; ++k) {
+                const float w = ph.v[j * kMaxK + k];   // 0 for k >= K
+                acc.x += w * v[k].x;
+                acc.y += w * v[k].y;
+            }
+            o[j * N + n] = acc;
+        }
+    }
+}
+
+hipError_t launch_backproject(const ClassArgs& a, int s0, int count, int nte, const float* phi_te, float2* out,
+                              hipStream_t st) {
+    PhiTe ph{};
+    for (int j = 0; j < nte; ++j)
+        for (int k = 0; k < a.K; ++k) ph.v[j * kMaxK + k] = phi_te[j * a.K + k];
+    const size_t N = (size_t)a.ny * a.nz;
+    const int gx = (int)std::min<size_t>((N + kThreads - 1) / kThreads, 1024);
+    hipLaunchKernelGGL(k_backproject, dim3(gx, count), dim3(kThreads), 0, st, a, s0, nte, ph, out);
+    return hipGetLastError();
+}
+
 // v[s] /= ||p[s]|| with ||p||^2 from the pass-A partials (0 when the norm is 0): the
 // renormalisation of the power iteration for the largest eigenvalue of A^H A
 __global__ __launch_bounds__(kThreads) void k_normalize(ClassArgs a, int s0, float2* v) {

@@ -91,6 +91,12 @@ hipError_t launch_init(const ClassArgs& a, int s0, int count, const float2* alph
 // momentum of the slice's counter (mode kLlrFista; step used only there)
 hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, const float2* in, float2* out,
                       float tau, int sy, int sz, float step, hipStream_t st);
+// post-step: in-place `levels`-level (1..4) orthonormal 2D Haar soft-threshold of every
+// coefficient image of alpha (ny, nz multiples of 16), slices [s0, s0 + count)
+hipError_t launch_haar_denoise(const ClassArgs& a, int s0, int count, int levels, float thr, hipStream_t st);
+// out[s - s0][j] = sum_k phi_te[j][k] alpha[s][k] (phi_te host [nte][K], nte <= kMaxK)
+hipError_t launch_backproject(const ClassArgs& a, int s0, int count, int nte, const float* phi_te, float2* out,
+                              hipStream_t st);
 // readout pre-step: out[x][c][p] = centred unitary inverse DFT over kx of in[c][p][kx]
 // (nx a supported FFT length, 0 < C <= 65535, P >= 0; in and out must not overlap)
 hipError_t launch_readout_ifft(int nx, int C, int P, const float2* in, float2* out, hipStream_t st);

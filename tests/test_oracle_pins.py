@@ -72,6 +72,46 @@ def test_readout_ifft_matches_inverse_dft(nx):
     assert rel(np.moveaxis(out, 0, -1) @ D.T, k) < 1e-12
 
 
+def test_haar_closed_forms_and_orthonormality():
+    # a constant image has only an approximation band (2 c per 2 x 2 block for the
+    # orthonormal transform); a +-1 pattern along z only the z-detail band
+    LL, LH, HL, HH = O.haar2(np.full((4, 6), 3.0 + 1j))
+    assert np.allclose(LL, 2 * (3.0 + 1j)) and not LH.any() and not HL.any() and not HH.any()
+    z = np.tile([1.0, -1.0, 1.0, -1.0], (4, 1))
+    LL, LH, HL, HH = O.haar2(z)
+    assert not LL.any() and np.allclose(LH, 2.0) and not HL.any() and not HH.any()
+    rng = np.random.default_rng(25)
+    x = crandn(rng, 3, 16, 8)
+    parts = O.haar2(x)
+    assert abs(sum(np.linalg.norm(p) ** 2 for p in parts) - np.linalg.norm(x) ** 2) < 1e-10 * np.linalg.norm(x) ** 2
+    assert rel(O.ihaar2(*parts), x) < 1e-14
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 4])
+def test_wavelet_denoise_limits(levels):
+    rng = np.random.default_rng(26 + levels)
+    x = crandn(rng, 2, 32, 48)
+    # no threshold: identity; infinite threshold: every aligned 2^J square becomes its mean
+    assert rel(O.wavelet_denoise(x, levels, 0.0), x) < 1e-13
+    B = 2 ** levels
+    means = x.reshape(2, 32 // B, B, 48 // B, B).mean(axis=(2, 4))
+    want = np.repeat(np.repeat(means, B, axis=1), B, axis=2)
+    assert rel(O.wavelet_denoise(x, levels, 1e30), want) < 1e-13
+    # shrinking never increases the energy of the detail bands, so the result is closer
+    # to the square means than the input is
+    y = O.wavelet_denoise(x, levels, 0.5)
+    assert np.linalg.norm(y - want) < np.linalg.norm(x - want)
+
+
+def test_backproject_recovers_images_in_the_subspace():
+    rng = np.random.default_rng(27)
+    phi, _ = np.linalg.qr(rng.standard_normal((12, 3)))
+    imgs = np.tensordot(phi, crandn(rng, 3, 8, 8), axes=(1, 0))      # a time series in span(Phi)
+    alpha = np.tensordot(phi.T, imgs, axes=(1, 0))                    # its coefficients (eq. backproj inverted)
+    sel = [1, 5, 11]
+    assert rel(O.backproject(alpha, phi[sel]), imgs[sel]) < 1e-13
+
+
 # --- T2: centring by +-1 modulation (FFTmod, Sec. IV-A) and the shifted kernel -------------
 
 
