@@ -1144,46 +1144,76 @@ hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, co
 // readout samples; out [L][C][P]: slice x, coil, sample (what t2s_load_slices reads).
 // Centred like the 2D transform: index kx is frequency kx - L/2 and x is position
 // x - L/2, so X[x] = (-1)^(x + L/2) L^-1/2 sum_kx (-1)^kx Y[kx] exp(+2 pi i kx x / L).
-// A workgroup transforms `readout_lines` consecutive entries of one coil in LDS
-// (measured at 320 and 512 points: 8 lines, 64-byte output runs, 2.0x faster than 4;
-// 16 lines need 87-140 KB of LDS and run fewer workgroups per CU, 1.7x slower).
+// A workgroup transforms `readout_lines` consecutive entries of one coil with the
+// register two-step plan of the solver passes (one LDS exchange per transform) and
+// stages the result through the same LDS so the stores go out with the entry index
+// fastest: 16 entries give 128-byte runs (74 KB of LDS at 512 points; 8 entries there
+// measured 11 % slower).  The LDS Stockham version (4 or 8 entries per workgroup) ran
+// at 1.2-2.5 TB/s.
 // ---------------------------------------------------------------------------
 template <int L>
-constexpr int readout_lines() { return L <= 128 ? 16 : 8; }
+constexpr int readout_lines() { return 16; }
+template <int L>
+constexpr int readout_lds() {
+    constexpr int a = readout_lines<L>() * RegGeom<L>::TB, b = L * (readout_lines<L>() + 1);
+    return a > b ? a : b;
+}
 
 template <int L>
-__global__ __launch_bounds__(kThreads) void k_readout_ifft(const float2* __restrict__ in, float2* __restrict__ out,
-                                                           int C, int P) {
-    constexpr int LT = readout_lines<L>(), LD = lds_ld(L);
+__global__ __launch_bounds__(readout_lines<L>() * RegGeom<L>::P) void k_readout_ifft(const float2* __restrict__ in,
+                                                                                   float2* __restrict__ out, int C,
+                                                                                   int P) {
+    using G = RegGeom<L>;
+    constexpr int R1 = G::R1, R2 = G::R2, PT = G::P, TB = G::TB, LT = readout_lines<L>(), NT = LT * PT;
     __shared__ float2 tw[L];
-    __shared__ float2 bufa[LT * LD];
-    __shared__ float2 bufb[LT * LD];
+    __shared__ float2 xb[readout_lds<L>()];
     const int c = blockIdx.y;
     const int p0 = blockIdx.x * LT;
-    const int nl = min(LT, P - p0);
-    for (int m = threadIdx.x; m < L; m += kThreads) {
+    const int tid = threadIdx.x;
+    const int line = tid / PT, th = tid - line * PT;
+    const bool ok = p0 + line < P;
+    for (int m = tid; m < L; m += NT) {
         double sn, cs;
         sincospi(-2.0 * m / L, &sn, &cs);
         tw[m] = make_float2((float)cs, (float)sn);
     }
-    // the tile of nl lines is one contiguous run of nl L values
-    const float2* src = in + ((size_t)c * P + p0) * L;
-    for (int i = threadIdx.x; i < LT * L; i += kThreads) {
-        const int t = i / L, j = i - t * L;
-        float2 v = make_float2(0.f, 0.f);
-        if (t < nl) v = ld_stream<true>(&src[i]);
-        if (j & 1) v = make_float2(-v.x, -v.y);
-        bufa[t * LD + ph(j)] = v;
+    __syncthreads();
+    float2* xw = xb + line * TB;
+    // step 1: thread th < R1 holds Y[th + R1 k2] (k2 < R2), with the (-1)^kx centring sign
+    if (th < R1) {
+        const float2* src = in + ((size_t)c * P + p0 + line) * L + th;
+        float2 b[R2];
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+            float2 v = make_float2(0.f, 0.f);
+            if (ok) v = ld_stream<true>(&src[R1 * k2]);
+            b[k2] = ((th + R1 * k2) & 1) ? make_float2(-v.x, -v.y) : v;
+        }
+        dft_dir<R2, true>(b);
+#pragma unroll
+        for (int m1 = 0; m1 < R2; ++m1) xw[m1 * (R1 + 1) + th] = tw_mul<true>(b[m1], tw, th * m1);
     }
     __syncthreads();
-    const float2* r = fft_lds<L, true>(bufa, bufb, LT, LD, tw);
+    // step 3: thread th < R2 ends with x[th + R2 m2] (m2 < R1)
+    float2 v[R1];
+    if (th < R2) {
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) v[k1] = xw[th * (R1 + 1) + k1];
+        dft_dir<R1, true>(v);
+    }
+    __syncthreads();
+    if (th < R2) {
+#pragma unroll
+        for (int m2 = 0; m2 < R1; ++m2) xb[(th + R2 * m2) * (LT + 1) + line] = v[m2];
+    }
+    __syncthreads();
     const float sc = (float)(1.0 / sqrt((double)L));
-    for (int i = threadIdx.x; i < LT * L; i += kThreads) {
+    for (int i = tid; i < LT * L; i += NT) {
         const int x = i / LT, t = i - x * LT;
-        if (t < nl) {
-            const float2 v = r[t * LD + ph(x)];
+        if (p0 + t < P) {
+            const float2 r = xb[x * (LT + 1) + t];
             const float f = ((x + L / 2) & 1) ? -sc : sc;
-            st_stream<true>(&out[((size_t)x * C + c) * P + p0 + t], make_float2(v.x * f, v.y * f));
+            st_stream<true>(&out[((size_t)x * C + c) * P + p0 + t], make_float2(r.x * f, r.y * f));
         }
     }
 }
@@ -1194,7 +1224,7 @@ hipError_t launch_readout_ifft(int nx, int C, int P, const float2* in, float2* o
 #define X(L)                                                                                                   \
     case L: {                                                                                                  \
         const dim3 grid((P + readout_lines<L>() - 1) / readout_lines<L>(), C);                                 \
-        hipLaunchKernelGGL(k_readout_ifft<L>, grid, dim3(kThreads), 0, st, in, out, C, P);                    \
+        hipLaunchKernelGGL(k_readout_ifft<L>, grid, dim3(readout_lines<L>() * RegGeom<L>::P), 0, st, in, out, C, P); \
         break;                                                                                                 \
     }
         X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
