@@ -133,6 +133,55 @@ def test_plan_state_errors_without_gpu():
     assert L.t2s_plan_destroy(h) == 0
 
 
+def test_fista_pre_and_post_step_validation_without_gpu():
+    """Argument and state checks of the FISTA, readout pre-step and post-step entry
+    points all run before any HIP call."""
+    L = T.lib()
+    buf = np.zeros(16, np.complex64)
+    p = buf.ctypes.data
+    # readout pre-step: shape checks first; an empty array needs no pointers
+    assert L.t2s_readout_ifft(100, 2, 10, p, p + 8, None) == T.T2S_ESHAPE     # no FFT plan for 100
+    assert L.t2s_readout_ifft(64, 0, 10, p, p + 8, None) == T.T2S_ESHAPE
+    assert L.t2s_readout_ifft(64, 2, -1, p, p + 8, None) == T.T2S_ESHAPE
+    assert L.t2s_readout_ifft(64, 2, 0, None, None, None) == 0
+    assert L.t2s_readout_ifft(64, 2, 10, None, p, None) == T.T2S_EINVAL
+    assert L.t2s_readout_ifft(64, 1, 1, p, p + 8, None) == T.T2S_EINVAL        # overlapping arrays
+    phi = _phi()
+    cls, _ = _classes()
+    code, h = _create(phi, cls)
+    assert code == 0
+    f = ctypes.c_float
+    # FISTA: mode, iteration count and step checked, then the state (nothing bound)
+    assert L.t2s_fista(None, T.T2S_BATCHED, 5, f(0.5), None) == T.T2S_EINVAL
+    assert L.t2s_fista(h, T.T2S_BATCHED_GRAPH, 5, f(0.5), None) == T.T2S_EINVAL
+    assert L.t2s_fista(h, T.T2S_BATCHED, -1, f(0.5), None) == T.T2S_EINVAL
+    assert L.t2s_fista(h, T.T2S_BATCHED, 5, f(0.0), None) == T.T2S_EINVAL
+    assert L.t2s_fista(h, T.T2S_BATCHED, 5, f(float("inf")), None) == T.T2S_EINVAL
+    assert L.t2s_fista(h, T.T2S_BATCHED, 5, f(0.5), None) == T.T2S_ESTATE
+    Lv = np.zeros(1)
+    dp = Lv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.t2s_lipschitz(h, 0, 0, dp, None) == T.T2S_EINVAL
+    assert L.t2s_lipschitz(h, 1, 10, dp, None) == T.T2S_EINVAL                   # no class 1
+    assert L.t2s_lipschitz(h, 0, 10, None, None) == T.T2S_EINVAL
+    assert L.t2s_lipschitz(h, 0, 10, dp, None) == T.T2S_ESTATE
+    # post-step
+    assert L.t2s_wavelet_denoise(h, 0, 0, 1, 0, f(0.1), None) == T.T2S_EINVAL
+    assert L.t2s_wavelet_denoise(h, 0, 0, 1, 5, f(0.1), None) == T.T2S_EINVAL
+    assert L.t2s_wavelet_denoise(h, 0, 0, 1, 2, f(-1.0), None) == T.T2S_EINVAL
+    assert L.t2s_wavelet_denoise(h, 0, 0, 2, 2, f(0.1), None) == T.T2S_EINVAL    # slices past the class
+    assert L.t2s_wavelet_denoise(h, 0, 0, 1, 2, f(0.1), None) == T.T2S_ESTATE
+    rows = np.zeros((9, 3), np.float32)
+    rp = rows.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    assert L.t2s_backproject(h, 0, 0, 1, 9, rp, p, None) == T.T2S_EINVAL         # more than 8 echo times
+    assert L.t2s_backproject(h, 0, 0, 1, 0, rp, p, None) == T.T2S_EINVAL
+    assert L.t2s_backproject(h, 0, 0, 1, 2, None, p, None) == T.T2S_EINVAL
+    rows[1, 2] = np.nan
+    assert L.t2s_backproject(h, 0, 0, 1, 2, rp, p, None) == T.T2S_ENONFINITE
+    rows[1, 2] = 0.0
+    assert L.t2s_backproject(h, 0, 0, 1, 2, rp, p, None) == T.T2S_ESTATE
+    assert L.t2s_plan_destroy(h) == 0
+
+
 def test_schedule_and_order_validation():
     phi = _phi()
     cls, masks = _classes()
