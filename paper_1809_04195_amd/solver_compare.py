@@ -1,6 +1,7 @@
 """ADMM with 5 CG steps per outer iteration against FISTA (the paper's solver, Sec. II-A,
 Table 1) on the 320-slice 256^2 volume (C=8, T=80, K=4): time per volume and the
-objective reached after given iteration counts, both solvers batched on one MI355X.
+objective reached after given iteration counts, both solvers batched on one MI355X
+(and FISTA once more with one launch sequence per slice, the plain schedule).
 
     python -m paper_1809_04195_amd.solver_compare [--admm 10,20,50,100,200]
         [--fista 50,100,250,500,1000] [--eval-slices 16]
@@ -53,6 +54,8 @@ def main():
     ap.add_argument("--fista", default="50,100,250,500,1000", help="FISTA iteration counts")
     ap.add_argument("--eval-slices", type=int, default=16)
     ap.add_argument("--power-iters", type=int, default=30)
+    ap.add_argument("--fista-plain", type=int, default=100,
+                    help="also time this many FISTA iterations with one launch sequence per slice (0: skip)")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
 
@@ -137,6 +140,18 @@ def main():
         f = objective(p)
         res["fista"].append(dict(iterations=n, normal_ops=n, s_per_volume=round(el, 4), objective=f))
         log(f"FISTA {n}: {el:.3f} s/volume, objective {f:.6e}")
+    if args.fista_plain:
+        n = args.fista_plain
+        load(p)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        load(p)
+        p.fista(n, step, mode=T.T2S_PER_SLICE)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        f = objective(p)
+        res["fista_per_slice"] = dict(iterations=n, s_per_volume=round(el, 4), objective=f)
+        log(f"FISTA {n}, per-slice launches: {el:.3f} s/volume, objective {f:.6e}")
     p.close()
 
     # iterations and time to reach the objective of the bench schedule (ADMM 100 x 5)
