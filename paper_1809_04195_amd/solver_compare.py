@@ -56,6 +56,8 @@ def main():
     ap.add_argument("--power-iters", type=int, default=30)
     ap.add_argument("--fista-plain", type=int, default=100,
                     help="also time this many FISTA iterations with one launch sequence per slice (0: skip)")
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="processes for input synthesis (0: auto); use 1 under a counter profiler (no child processes)")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
 
@@ -66,7 +68,7 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     t0 = time.perf_counter()
-    d = make_config(1)
+    d = make_config(1, workers=args.gen_workers or None)
     cfg, phi, cl = d["cfg"], d["phi"], d["classes"][0]
     S, K, b, lam = cl.nslices, phi.shape[1], cfg["block"], cfg["lam"]
     log(f"volume {S} x {cl.ny}x{cl.nz} C{cl.ncoils} generated in {time.perf_counter() - t0:.1f} s")
