@@ -20,6 +20,7 @@
 namespace unetk {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef uint16_t bf16;
 
@@ -38,6 +39,12 @@ __host__ __device__ inline float bf2f(bf16 h) {
 }
 
 constexpr int kNT = 256;
+
+__device__ __forceinline__ bf16x4 lo4(bf16x8 v) { return __builtin_shufflevector(v, v, 0, 1, 2, 3); }
+__device__ __forceinline__ bf16x4 hi4(bf16x8 v) { return __builtin_shufflevector(v, v, 4, 5, 6, 7); }
+__device__ __forceinline__ void Bv8_load(bf16x8& dst, bool ok, const uint16_t* p) {
+    dst = ok ? *(const bf16x8*)p : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+}
 
 // ---------------------------------------------------------------------------
 // implicit-GEMM convolution: out[p][co] = bias[co] + sum_{tap, ci} W[tap][co][ci] in[p + off(tap)][ci]
@@ -96,7 +103,30 @@ __global__ __launch_bounds__(kNT) void k_conv(ConvArgs a) {
             src[j] = a.in + ((size_t)(pb[j] * a.H + (ok[j] ? y : 0)) * a.W + (ok[j] ? x : 0)) * a.ldi + a.ci_off;
         }
         const bf16* wt = a.w + (size_t)tap * a.coutp * a.cinp;
-        for (int ci0 = 0; ci0 < a.cinp; ci0 += 16) {
+        int ci0 = 0;
+        // 32 channels per step: each lane loads 8 consecutive channels (16 bytes) of A and B
+        // and feeds two MFMAs with the two halves.  The reduction index is permuted
+        // (MFMA k = 4 q + r of the first half is channel 8 q + r, of the second 8 q + 4 + r)
+        // identically for A and B, which leaves the sum unchanged
+        for (; ci0 + 32 <= a.cinp; ci0 += 32) {
+            const int ci = ci0 + 8 * q;
+            bf16x8 A8[2], B8[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int co = co_w + i * 16 + r16;
+                A8[i] = co < a.coutp ? *(const bf16x8*)(wt + (size_t)co * a.cinp + ci) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) Bv8_load(B8[j], ok[j], src[j] + ci);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lo4(A8[i]), lo4(B8[j]), acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hi4(A8[i]), hi4(B8[j]), acc[i][j], 0, 0, 0);
+                }
+        }
+        for (; ci0 < a.cinp; ci0 += 16) {
             const int ci = ci0 + 4 * q;
             bf16x4 A[2], Bv[2];
 #pragma unroll
