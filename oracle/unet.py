@@ -238,3 +238,24 @@ def unpack_channels(x, scale):
     H, W, C = x.shape
     v = x.reshape(H, W, C // 2, 2).transpose(2, 0, 1, 3)
     return scale * (v[..., 0] + 1j * v[..., 1])
+
+
+# ---------------------------------------------------------------------------
+# optimiser: Adam (Kingma & Ba, "Adam: a method for stochastic optimization",
+# ICLR 2015, Algorithm 1), FP64
+# ---------------------------------------------------------------------------
+
+
+def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Update number t >= 1 of the parameters w with gradient g from moments (m, v):
+    m <- beta1 m + (1 - beta1) g,  v <- beta2 v + (1 - beta2) g^2,
+    m_hat = m / (1 - beta1^t),  v_hat = v / (1 - beta2^t),
+    w <- w - lr m_hat / (sqrt(v_hat) + eps).
+    Returns (w, m, v)."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

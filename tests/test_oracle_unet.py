@@ -79,3 +79,49 @@ def test_pack_round_trip():
     assert x.shape == (6, 8, 8)
     assert np.isclose(x[1, 2, 3], a[1, 1, 2].imag / 2.5) and np.isclose(x[1, 2, 2], a[1, 1, 2].real / 2.5)
     assert np.allclose(U.unpack_channels(x, 2.5), a)
+
+
+# --- Adam (Kingma & Ba 2015, Algorithm 1) ---------------------------------------------
+
+
+def test_adam_constant_gradient_moves_every_weight_by_lr():
+    """With a constant gradient the bias corrections make m_hat = g and v_hat = g^2 exactly
+    at every step, so each step moves w by lr g / (|g| + eps): a wrong decay, a swapped beta,
+    a missing correction or a missing square root breaks this."""
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal(50) * 10.0 ** rng.uniform(-3, 3, 50)
+    w = rng.standard_normal(50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    lr = 1e-3
+    for t in range(1, 8):
+        w_new, m, v = U.adam_step(w, g, m, v, t, lr)
+        np.testing.assert_allclose(w - w_new, lr * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=1e-15)
+        w = w_new
+
+
+def test_adam_second_step_after_zero_gradient():
+    """Step 1 with g, step 2 with 0: m_hat_2 = beta1 (1 - beta1) g / (1 - beta1^2) = beta1 g / (1 + beta1),
+    v_hat_2 = beta2 g^2 / (1 + beta2); the second move is lr m_hat_2 / (sqrt(v_hat_2) + eps)."""
+    g = np.array([2.0, -0.5, 3e-3])
+    w0 = np.array([1.0, 2.0, 3.0])
+    lr = 0.01
+    w1, m, v = U.adam_step(w0, g, np.zeros(3), np.zeros(3), 1, lr)
+    w2, m, v = U.adam_step(w1, np.zeros(3), m, v, 2, lr)
+    m_hat = 0.9 * g / 1.9
+    v_hat = 0.999 * g * g / 1.999
+    np.testing.assert_allclose(w1 - w2, lr * m_hat / (np.sqrt(v_hat) + 1e-8), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.9 * 0.1 * g, rtol=1e-12)
+    np.testing.assert_allclose(v, 0.999 * 0.001 * g * g, rtol=1e-12)
+
+
+def test_adam_descends_a_quadratic():
+    """Adam on f(w) = 1/2 ||w - w*||^2 with a decaying rate ends near the minimiser."""
+    rng = np.random.default_rng(1)
+    target = rng.standard_normal(20)
+    w = np.zeros(20)
+    m = np.zeros(20)
+    v = np.zeros(20)
+    for t in range(1, 3001):
+        w, m, v = U.adam_step(w, w - target, m, v, t, 0.05 / np.sqrt(t))
+    assert np.abs(w - target).max() < 1e-2
