@@ -68,6 +68,8 @@ extern "C" {
 #define T2S_Z 1
 #define T2S_U 2
 #define T2S_ADJOINT 3   /* b0 = A^H y of the loaded samples */
+#define T2S_RESIDUAL 4  /* CG residual r = b0 + rho (z - u) - (A^H A + rho I) alpha, kept
+                           up to date by the z-step for the next alpha-step */
 
 #define T2S_MAX_K 8
 
@@ -138,19 +140,38 @@ int t2s_plan_bind_workspace(t2s_plan* plan, void* device_ptr, size_t bytes, void
 /* Load slices [first, first + count) of class `cls`: coil maps sens
  * (complex64 [count][ncoils][ny][nz]) and samples ksp (complex64
  * [count][ncoils][P_tot], mask order), both in `mem`, and compute the adjoint
- * b0 = A^H y = sum_c conj(S_c) F^H (Phi^T P^H y_c) on the device.  Resets the
- * slices to the cold start alpha = z = u = 0.  Host inputs are checked for
- * NaN / Inf (T2S_ENONFINITE). */
+ * b0 = A^H y = sum_c conj(S_c) F^H (Phi^T P^H y_c) on the device.
+ * The samples are the data y of eq. t2shpics (Sec. II-B) in the truncated form of
+ * Sec. II-A (P in {0,1}^{P x N} keeps only the acquired entries of each echo); the
+ * projection onto the basis and the re-sorting by k-space location are the "re-sort
+ * and project" step of Sec. III-A, done here per slice on the device; the maps are
+ * S of eq. coilmodel.  Resets the slices to the cold start alpha = z = u = 0.
+ * Host inputs are checked for NaN / Inf (T2S_ENONFINITE).  Host buffers are copied
+ * before the call returns; device buffers must stay valid until `stream` has run
+ * the load.  Errors: T2S_EINVAL (NULL, class or slice range, mem), T2S_ESTATE
+ * (workspace not bound), T2S_ENONFINITE, T2S_EHIP. */
 int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* sens,
                     const void* ksp, int mem, void* stream);
 
-/* Warm start: alpha = z = alpha0 (complex64 [count][K][ny][nz] in `mem`), u = 0.
- * Must follow t2s_load_slices for these slices. */
+/* Warm start: alpha = z = alpha0 (complex64 [count][K][ny][nz] in `mem`), u = 0, and
+ * the CG residual r = b0 - A^H A alpha0.  The paper starts its iteration from zero
+ * (Sec. II-A: FISTA on eq. t2shpics); any start reaches the same minimiser of the
+ * convex problem at a fixed block shift, so the start only changes how many
+ * iterations the stop rule of t2s_reconstruct needs.  Must follow t2s_load_slices
+ * for these slices.  Host alpha0 is checked for NaN / Inf and copied before the call
+ * returns.  Errors: T2S_EINVAL, T2S_ESTATE (slice not loaded), T2S_ENONFINITE,
+ * T2S_EHIP. */
 int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* alpha0,
                     int mem, void* stream);
 
-/* Run ADMM on every loaded slice.  mode = T2S_BATCHED or T2S_PER_SLICE (same
- * arithmetic, different launch schedule).  Fixed mode (tol == 0) is fully
+/* Solve eq. t2shpics (Sec. II-B) for every loaded slice independently (the
+ * per-slice decoupling of Sec. II-A end / Sec. IV-E): scaled ADMM (Boyd et al. 2011,
+ * Sec. 3.1.1) with z-step = the blocked LLR prox of Sec. II-B end / Sec. IV-C at
+ * threshold lambda / rho, u-step u += alpha - z, and alpha-step n_cg CG iterations on
+ * (A^H A + rho I) alpha = b0 + rho (z - u) with A^H A applied through Psi (Sec. IV-B,
+ * Alg. 1).  mode = T2S_BATCHED, T2S_BATCHED_GRAPH or T2S_PER_SLICE (same
+ * arithmetic, different launch schedule).  Errors: T2S_EINVAL (mode), T2S_ESTATE
+ * (workspace not bound or a slice not loaded), T2S_EHIP.  Fixed mode (tol == 0) is fully
  * asynchronous.  Tolerance mode synchronises `stream` every check_every outer
  * iterations to read the per-slice residuals and decides per slice, in this order:
  * stop if max(r_p, r_d) <= tol; else freeze the block shift at the current draw if
@@ -191,9 +212,12 @@ int t2s_get_order(const t2s_plan* plan, int cls, int* order);
  * Synchronises `stream`. */
 int t2s_autotune(t2s_plan* plan, int reps, void* stream);
 
-/* Copy out alpha, z, u or b0 (which = T2S_ALPHA / T2S_Z / T2S_U / T2S_ADJOINT) of
- * slices [first, first + count) as complex64 [count][K][ny][nz] into `out` (`mem`).
- * A host destination synchronises `stream`. */
+/* Copy out alpha, z, u, b0 or r (which = T2S_ALPHA / T2S_Z / T2S_U / T2S_ADJOINT /
+ * T2S_RESIDUAL) of slices [first, first + count) as complex64 [count][K][ny][nz] into
+ * `out` (`mem`).  alpha is the solution of eq. t2shpics: the subspace coefficient
+ * images of eq. backproj (Sec. II-B), from which x_t = sum_k Phi_tk alpha_k gives the
+ * image at echo t (t2s_backproject).  A host destination synchronises `stream`.
+ * Errors: T2S_EINVAL (NULL, range, which, mem), T2S_ESTATE, T2S_EHIP. */
 int t2s_read_coeffs(t2s_plan* plan, int cls, int first, int count, void* out, int which,
                     int mem, void* stream);
 
@@ -348,6 +372,16 @@ int t2s_unet_train_step(t2s_unet* net, const void* b0, const void* target, int B
  * targets t, both [B][H][W][2K] (already normalised).  Synchronous. */
 int t2s_unet_loss_grad(t2s_unet* net, const float* x, const float* t, int B, double* loss, float* grad,
                        void* stream);
+/* Verification entries of the optimiser: one Adam step of the training path (the
+ * update t2s_unet_train_step applies after its backward pass: beta 0.9 / 0.999,
+ * eps 1e-8, bias-corrected moments, step counter + 1, then the bf16 weight copies)
+ * with the gradient taken from host `grad` (param_count floats, checked for NaN /
+ * Inf) instead of the backward pass; synchronous.  And the optimiser state: first and
+ * second moments m, v (host, param_count floats each) and the step count.
+ * Errors: T2S_EINVAL, T2S_ESTATE (workspace not bound), T2S_ENONFINITE, T2S_EHIP. */
+int t2s_unet_adam_apply(t2s_unet* net, const float* grad, float lr, void* stream);
+int t2s_unet_get_adam_state(t2s_unet* net, float* m, float* v, int* step, void* stream);
+
 /* Initial parameters into host `params` (param_count floats): He-normal weights
  * (standard deviation sqrt(2 / fan_in)) from a 64-bit Mersenne twister seeded with
  * `seed`, zero biases, the final 1x1 layer scaled by 0.1. */

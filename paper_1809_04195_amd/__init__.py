@@ -37,6 +37,7 @@ T2S_ALPHA = 0
 T2S_Z = 1
 T2S_U = 2
 T2S_ADJOINT = 3
+T2S_RESIDUAL = 4
 T2S_KERNEL_PASS_A = 0
 T2S_KERNEL_PASS_B = 1
 T2S_KERNEL_PASS_C = 2
@@ -150,6 +151,10 @@ _SIGS = {
                             ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
                             ctypes.c_void_p], ctypes.c_int),
     "t2s_unet_init_params": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "t2s_unet_adam_apply": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_float, ctypes.c_void_p],
+                            ctypes.c_int),
+    "t2s_unet_get_adam_state": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_int), ctypes.c_void_p], ctypes.c_int),
     "t2s_unet_mfma_probe": ([ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "t2s_block_shift": ([ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -526,6 +531,21 @@ class UNet:
         _check(lib().t2s_unet_loss_grad(self.handle, _fptr(x), _fptr(t), x.shape[0], ctypes.byref(loss), _fptr(g),
                                         _stream(stream)))
         return loss.value, g
+
+    def adam_apply(self, grad, lr, stream=None):
+        """One Adam step of the training path with the given host gradient."""
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        if g.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} gradient values, got {g.size}")
+        _check(lib().t2s_unet_adam_apply(self.handle, _fptr(g), lr, _stream(stream)))
+
+    def adam_state(self, stream=None):
+        """(m, v, step) of the optimiser."""
+        m = np.empty(self.nparams, dtype=np.float32)
+        v = np.empty(self.nparams, dtype=np.float32)
+        step = ctypes.c_int()
+        _check(lib().t2s_unet_get_adam_state(self.handle, _fptr(m), _fptr(v), ctypes.byref(step), _stream(stream)))
+        return m, v, step.value
 
     def close(self):
         if self.handle is not None:

@@ -527,8 +527,7 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.nrw = (ny / t2s::kRowTile) * K;
         const int wb = t2s::passB_columns(ny, K);
         c.npb = ((nz + wb - 1) / wb) * c.C;
-        const int strips = (ny / p->block) * ((nz + 63) / 64);
-        c.nllr = (strips + 3) / 4;
+        c.nllr = t2s::llr_workgroups(ny, nz, p->block);
         c.loaded.assign(c.S, 0);
         c.outer_run.assign(c.S, 0);
         c.k_freeze.assign(c.S, -1);
@@ -758,7 +757,9 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
         std::vector<std::vector<int>> active(plan->cls.size());
         for (size_t ci = 0; ci < plan->cls.size(); ++ci) active[ci].assign(plan->cls[ci].S, 1);
         std::vector<double> hbuf;
-        // ||b0|| of every slice (partials written when the slice was loaded)
+        // ||b0|| of every slice (partials written when the slice was loaded, on this
+        // stream: wait for them before the synchronous read)
+        HIP_TRY(hipStreamSynchronize(st));
         std::vector<std::vector<double>> b0norm(plan->cls.size());
         for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
             const ClassPlan& c = plan->cls[ci];
@@ -962,6 +963,7 @@ int t2s_read_coeffs(t2s_plan* plan, int cls, int first, int count, void* out, in
         case T2S_Z: src = a.z; break;
         case T2S_U: src = a.u; break;
         case T2S_ADJOINT: src = a.b0; break;
+        case T2S_RESIDUAL: src = a.r; break;
         default: return fail(T2S_EINVAL, "bad `which`");
     }
     const size_t n = (size_t)plan->prm.K * c.ny * c.nz;

@@ -949,6 +949,12 @@ __global__ void k_llr_finalize(ClassArgs a, int s0) {
 
 bool fft_supported(int L) { return fft_length_supported(L); }
 
+int llr_workgroups(int ny, int nz, int b) {
+    if (b != 4 && b != 8 && b != 16) return 0;
+    const int strips = (ny / b) * ((nz + 63) / 64);   // one wave per strip of b rows x 64 columns
+    return (strips + kThreads / 64 - 1) / (kThreads / 64);
+}
+
 bool reg_plan(int L, int* R1, int* R2) {
     switch (L) {
 #define X(n)                          \

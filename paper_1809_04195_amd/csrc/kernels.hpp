@@ -109,6 +109,9 @@ hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, i
 hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, hipStream_t st);
 
 bool fft_supported(int L);
+// workgroups of the LLR kernel per slice (one partial-sum slot each); 0 for an
+// unsupported block size
+int llr_workgroups(int ny, int nz, int b);
 // two-step register plan L = R1 * R2 of the passes (false if L has no plan)
 bool reg_plan(int L, int* R1, int* R2);
 size_t lds_bytes_passA(int nz);

@@ -467,13 +467,15 @@ __global__ void k_prep(const float* master, int KS, int cout, int cin, int coutp
     if (wb) wb[((size_t)(taps - 1 - tap) * cinp + ci) * coutp + co] = f2bf(v);
 }
 
-__global__ void k_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
-                       float c1, float c2) {
+// omb1 = 1 - b1, omb2 = 1 - b2 and the bias corrections c1, c2 come from the host in
+// double precision (1 - b2 formed in fp32 from 0.999f would be off by 1.3e-5)
+__global__ void k_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
+                       float omb1, float omb2, float eps, float c1, float c2) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -677,6 +679,20 @@ int prep_all(t2s_unet* u, hipStream_t st) {
         ULAUNCH();
     }
     return 0;
+}
+
+// One Adam step (Kingma & Ba, with bias correction) on the fp32 master weights from
+// the gradient buffer, then the bf16 weight copies; advances the step counter.
+int adam_update(t2s_unet* u, float lr, hipStream_t st) {
+    u->step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const double c1 = 1.0 - std::pow(b1, (double)u->step), c2 = 1.0 - std::pow(b2, (double)u->step);
+    hipLaunchKernelGGL(unetk::k_adam, dim3((unsigned)((u->nparams + 255) / 256)), dim3(256), 0, st,
+                       at<float>(u, u->o_master), at<float>(u, u->o_g), at<float>(u, u->o_m), at<float>(u, u->o_v),
+                       u->nparams, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, (float)c1,
+                       (float)c2);
+    ULAUNCH();
+    return prep_all(u, st);
 }
 
 // forward pass on normalised input (x32, xb filled); y32 = net output (2K channels, ld cxp)
@@ -1049,14 +1065,31 @@ int t2s_unet_train_step(t2s_unet* u, const void* b0, const void* target, int B, 
     if (int e = forward(u, B, st)) return e;
     if (int e = loss_and_dy(u, B, loss, st)) return e;
     if (int e = backward(u, B, st)) return e;
-    u->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - std::pow(b1, (float)u->step), c2 = 1.f - std::pow(b2, (float)u->step);
-    hipLaunchKernelGGL(unetk::k_adam, dim3((unsigned)((u->nparams + 255) / 256)), dim3(256), 0, st,
-                       at<float>(u, u->o_master), at<float>(u, u->o_g), at<float>(u, u->o_m), at<float>(u, u->o_v),
-                       u->nparams, lr, b1, b2, 1e-8f, c1, c2);
-    ULAUNCH();
-    return prep_all(u, st);
+    return adam_update(u, lr, st);
+}
+
+int t2s_unet_adam_apply(t2s_unet* u, const float* grad, float lr, void* stream) {
+    if (!u || !grad) return ufail(T2S_EINVAL, "NULL argument");
+    if (!u->ws) return ufail(T2S_ESTATE, "workspace not bound");
+    if (!(lr > 0) || !std::isfinite(lr)) return ufail(T2S_EINVAL, "learning rate must be > 0");
+    for (size_t i = 0; i < u->nparams; ++i)
+        if (!std::isfinite(grad[i])) return ufail(T2S_ENONFINITE, "gradient contains NaN/Inf");
+    hipStream_t st = (hipStream_t)stream;
+    UHIP(hipMemcpyAsync(u->ws + u->o_g, grad, u->nparams * 4, hipMemcpyHostToDevice, st));
+    if (int e = adam_update(u, lr, st)) return e;
+    UHIP(hipStreamSynchronize(st));
+    return 0;
+}
+
+int t2s_unet_get_adam_state(t2s_unet* u, float* m, float* v, int* step, void* stream) {
+    if (!u || !m || !v || !step) return ufail(T2S_EINVAL, "NULL argument");
+    if (!u->ws) return ufail(T2S_ESTATE, "workspace not bound");
+    hipStream_t st = (hipStream_t)stream;
+    UHIP(hipMemcpyAsync(m, u->ws + u->o_m, u->nparams * 4, hipMemcpyDeviceToHost, st));
+    UHIP(hipMemcpyAsync(v, u->ws + u->o_v, u->nparams * 4, hipMemcpyDeviceToHost, st));
+    UHIP(hipStreamSynchronize(st));
+    *step = u->step;
+    return 0;
 }
 
 int t2s_unet_loss_grad(t2s_unet* u, const float* x, const float* t, int B, double* loss, float* grad, void* stream) {
