@@ -391,6 +391,16 @@ int t2s_unet_init_params(const t2s_unet* net, uint64_t seed, float* params);
  * on input) -- a check of the lane layout the convolution kernels assume. */
 int t2s_unet_mfma_probe(const float* A, const float* B, float* D);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the product of t2s_unet_mfma_probe
+ * for `count` tiles (A, B, D host fp32 [count][16][16], D[i] = A[i] B[i]) with its
+ * device staging in a static per-device buffer of the library instead of memory it
+ * allocates, so the call performs no device allocation.  count must be in [1, 8] (the
+ * buffer holds 8 tiles, 16 KiB); larger counts return T2S_EINVAL.  Synchronous.
+ * Every call on a device shares that device's buffer: calls that overlap on one GPU
+ * (from several host threads) race.  Errors: T2S_EINVAL, T2S_EHIP. */
+int t2s_unet_mfma_probe_static(const float* A, const float* B, float* D, int count);
+
 #ifdef __cplusplus
 }
 #endif

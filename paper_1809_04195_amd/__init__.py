@@ -157,6 +157,8 @@ _SIGS = {
                                 ctypes.POINTER(ctypes.c_int), ctypes.c_void_p], ctypes.c_int),
     "t2s_unet_mfma_probe": ([ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "t2s_unet_mfma_probe_static": ([ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                    ctypes.POINTER(ctypes.c_float), ctypes.c_int], ctypes.c_int),
     "t2s_block_shift": ([ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                          ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
 }
@@ -474,6 +476,17 @@ def t2s_unet_mfma_probe(A, B):
     B = np.ascontiguousarray(B, dtype=np.float32)
     D = np.empty((16, 16), dtype=np.float32)
     _check(lib().t2s_unet_mfma_probe(_fptr(A), _fptr(B), _fptr(D)))
+    return D
+
+
+def t2s_unet_mfma_probe_static(A, B):
+    """A, B: [count, 16, 16]; D[i] = A[i] B[i] through the allocation-free entry point."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    if A.shape != B.shape or A.ndim != 3 or A.shape[1:] != (16, 16):
+        raise ValueError("A and B must both be [count, 16, 16]")
+    D = np.empty(A.shape, dtype=np.float32)
+    _check(lib().t2s_unet_mfma_probe_static(_fptr(A), _fptr(B), _fptr(D), A.shape[0]))
     return D
 
 

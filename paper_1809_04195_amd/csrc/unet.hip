@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdint>
 #include <cstring>
 #include <random>
@@ -481,9 +482,13 @@ __global__ void k_adam(float* w, const float* g, float* m, float* v, size_t n, f
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// single-tile MFMA check: D = A B (16 x 16 x 16, bf16 in, fp32 out), row-major operands
+// MFMA check: D = A B (16 x 16 x 16, bf16 in, fp32 out), row-major operands; tile
+// blockIdx.x of consecutive 256-element tiles
 __global__ void k_mfma_probe(const bf16* A, const bf16* B, float* D) {
     const int l = threadIdx.x;
+    A += blockIdx.x * 256;
+    B += blockIdx.x * 256;
+    D += blockIdx.x * 256;
     bf16x4 a, b;
     for (int r = 0; r < 4; ++r) {
         a[r] = (short)A[(l % 16) * 16 + 4 * (l / 16) + r];
@@ -492,6 +497,12 @@ __global__ void k_mfma_probe(const bf16* A, const bf16* B, float* D) {
     floatx4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     for (int r = 0; r < 4; ++r) D[(4 * (l / 16) + r) * 16 + l % 16] = d[r];
 }
+
+// Staging of the allocation-free probe (t2s_unet_mfma_probe_static): up to
+// kProbeMaxTiles A and B tiles (bf16) and D tiles (fp32).  Each device holds its own
+// copy; host code reaches it only through the address hipGetSymbolAddress returns.
+constexpr int kProbeMaxTiles = 8;
+__device__ __align__(256) unsigned char scratch[kProbeMaxTiles * (512 + 512 + 1024)];
 
 }  // namespace unetk
 
@@ -678,6 +689,24 @@ int prep_all(t2s_unet* u, hipStream_t st) {
                            at<bf16>(u, Ly.o_wf), at<bf16>(u, Ly.o_wb));
         ULAUNCH();
     }
+    return 0;
+}
+
+// Device address of unetk::scratch on the current device, looked up once per device
+// (the array's name is only a host-side stand-in for it).
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+int static_scratch(void** out) {
+    int dev = 0;
+    UHIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return ufail(T2S_EHIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        UHIP(hipGetSymbolAddress(&p, HIP_SYMBOL(unetk::scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return 0;
 }
 
@@ -1127,6 +1156,29 @@ int t2s_unet_init_params(const t2s_unet* u, uint64_t seed, float* host) {
         for (size_t i = 0; i < nw; ++i) host[Ly.woff + i] = (float)(sd * nd(gen));
         for (int i = 0; i < Ly.nbias; ++i) host[Ly.boff + i] = 0.f;
     }
+    return 0;
+}
+
+int t2s_unet_mfma_probe_static(const float* A, const float* B, float* D, int count) {
+    if (!A || !B || !D) return ufail(T2S_EINVAL, "NULL argument");
+    if (count < 1 || count > unetk::kProbeMaxTiles)
+        return ufail(T2S_EINVAL, "count must be in [1, " + std::to_string(unetk::kProbeMaxTiles) +
+                                     "]: the static staging buffer holds that many tiles");
+    bf16 a[unetk::kProbeMaxTiles * 256], b[unetk::kProbeMaxTiles * 256];
+    for (int i = 0; i < count * 256; ++i) {
+        a[i] = unetk::f2bf(A[i]);
+        b[i] = unetk::f2bf(B[i]);
+    }
+    void* sp = nullptr;
+    if (int e = static_scratch(&sp)) return e;
+    bf16* da = (bf16*)sp;
+    bf16* db = da + unetk::kProbeMaxTiles * 256;
+    float* dd = (float*)(db + unetk::kProbeMaxTiles * 256);
+    UHIP(hipMemcpy(da, a, (size_t)count * 512, hipMemcpyHostToDevice));
+    UHIP(hipMemcpy(db, b, (size_t)count * 512, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(unetk::k_mfma_probe, dim3(count), dim3(64), 0, 0, (const bf16*)da, (const bf16*)db, dd);
+    ULAUNCH();
+    UHIP(hipMemcpy(D, dd, (size_t)count * 1024, hipMemcpyDeviceToHost));
     return 0;
 }
 
