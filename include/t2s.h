@@ -92,10 +92,18 @@ typedef struct t2s_params {
 
 /* One shape class: slices sharing grid, coil count and sampling masks. */
 typedef struct t2s_class {
-    int ny, nz;            /* slice grid (even, multiples of block)                  */
+    int ny, nz;            /* slice grid: ny a column length with an FFT plan (a     */
+                           /* multiple of 16: 16 ... 512), nz a row length (those or  */
+                           /* 260); blocks are partial where b does not divide them   */
     int ncoils;            /* C >= 1                                                 */
     int nslices;           /* slices of this class held by the plan                  */
     const uint8_t* masks;  /* host [T][ny][nz], 1 = sampled; copied at creation      */
+    int nmaps;             /* coil-map sets M (soft-SENSE, Sec. II-A; Alg. 1's maps  */
+                           /* S_(i,0), S_(i,1)): 0 or 1 = one set, 2 = two.  With M   */
+                           /* sets the maps are [C][M][ny][nz] per slice, the unknown */
+                           /* has M K images ([M][K][ny][nz] per slice: K coefficient */
+                           /* images per set), coil c sees sum_m S_(c,m) x_m, and the */
+                           /* LLR blocks are taken per set                            */
 } t2s_class;
 
 /* Per-slice outcome of the last t2s_reconstruct. */
@@ -270,7 +278,7 @@ int t2s_wavelet_denoise(t2s_plan* plan, int cls, int first, int count, int level
                         void* stream);
 
 /* Back-projection onto echo times (eq. backproj): out[i][j] = sum_k phi_te[j][k]
- * alpha_k of slice first + i, for n_te (1..8) echo times whose basis rows phi_te
+ * alpha_k of slice first + i (with M coil-map sets, out[i][m][j] for every set m), for n_te (1..8) echo times whose basis rows phi_te
  * (host float [n_te][K], copied before the call returns) the caller gives, e.g. rows
  * of Phi at the desired echoes (the paper's TE 21 / 50 / 90 ms).  out: device
  * complex64 [count][n_te][ny][nz].  Errors: T2S_EINVAL, T2S_ENONFINITE, T2S_ESTATE,

@@ -19,7 +19,8 @@ reconstruction", arXiv 1809.04195):
 
 Array conventions (shared with the C ABI, as plain data):
   alpha        complex [K, Ny, Nz]          subspace coefficient images
-  sens         complex [C, Ny, Nz]          coil maps S_c (M = 1 map set)
+  sens         complex [C, Ny, Nz]          coil maps S_c (M = 1 map set), or
+               complex [C, M, Ny, Nz]       M soft-SENSE map sets (alpha then [M, K, Ny, Nz])
   phi          real    [T, K]               temporal basis
   masks        bool    [T, Ny, Nz]          centred sampling masks, DC at (Ny/2, Nz/2)
   samples      complex [C, P_tot]           measured k-space in *mask order*:
@@ -79,37 +80,54 @@ def mask_order(masks: np.ndarray):
 # ---------------------------------------------------------------------------
 
 
-def forward(alpha, sens, phi, masks):
-    """A alpha: samples[c, p] = (F(S_c x_t))[loc_p] with x_t = sum_k Phi[t,k] alpha_k, t = t_p."""
+# Soft-SENSE (Sec. II-A): with M sets of coil maps, sens is [C, M, Ny, Nz] and the
+# unknown has one set of K coefficient images per map set, alpha [M, K, Ny, Nz]; coil c
+# sees sum_m S_(c,m) x_m.  A [C, Ny, Nz] sens (M = 1) goes with alpha [K, Ny, Nz].
+
+
+def _maps(alpha, sens):
+    """(alpha [M, K, Ny, Nz], sens [C, M, Ny, Nz], single-set flag) in complex128."""
     alpha = np.asarray(alpha, dtype=np.complex128)
     sens = np.asarray(sens, dtype=np.complex128)
+    if sens.ndim == 3:
+        return alpha[None], sens[:, None], True
+    return alpha, sens, False
+
+
+def forward(alpha, sens, phi, masks):
+    """A alpha: samples[c, p] = (F(sum_m S_cm x_mt))[loc_p] with x_mt = sum_k Phi[t,k] alpha_mk, t = t_p."""
+    alpha, sens, _ = _maps(alpha, sens)
     phi = np.asarray(phi, dtype=np.float64)
     T = phi.shape[0]
-    C, Ny, Nz = sens.shape
+    C, M, Ny, Nz = sens.shape
     t_of, loc = mask_order(masks)
-    x = np.einsum("tk,kyz->tyz", phi, alpha)                    # back-projection to echoes
+    x = np.einsum("tk,mkyz->mtyz", phi, alpha)                  # back-projection to echoes, per map set
     out = np.empty((C, t_of.size), dtype=np.complex128)
     for c in range(C):
-        kspace = fft2c(sens[c][None] * x).reshape(T, Ny * Nz)   # [T, N] full k-space
+        img = np.einsum("myz,mtyz->tyz", sens[c], x)           # coil image sum_m S_cm x_m
+        kspace = fft2c(img).reshape(T, Ny * Nz)                 # [T, N] full k-space
         out[c] = kspace[t_of, loc]                              # P: keep sampled entries
     return out
 
 
 def adjoint(samples, sens, phi, masks):
-    """A^H y: zero-fill each echo, project onto the basis, inverse DFT, coil-combine."""
+    """A^H y: zero-fill each echo, project onto the basis, inverse DFT, combine each map
+    set's coils."""
     samples = np.asarray(samples, dtype=np.complex128)
-    sens = np.asarray(sens, dtype=np.complex128)
+    _, sens4, single = _maps(np.zeros(1), sens)
     phi = np.asarray(phi, dtype=np.float64)
     T, K = phi.shape
-    C, Ny, Nz = sens.shape
+    C, M, Ny, Nz = sens4.shape
     t_of, loc = mask_order(masks)
-    alpha = np.zeros((K, Ny, Nz), dtype=np.complex128)
+    alpha = np.zeros((M, K, Ny, Nz), dtype=np.complex128)
     for c in range(C):
         full = np.zeros((T, Ny * Nz), dtype=np.complex128)
         full[t_of, loc] = samples[c]                            # P^H: zero-fill
         proj = np.einsum("tk,tn->kn", phi, full).reshape(K, Ny, Nz)   # Phi^T
-        alpha += np.conj(sens[c])[None] * ifft2c(proj)          # S^H F^H
-    return alpha
+        img = ifft2c(proj)                                      # F^H
+        for m in range(M):
+            alpha[m] += np.conj(sens4[c, m])[None] * img        # S_cm^H
+    return alpha[0] if single else alpha
 
 
 # ---------------------------------------------------------------------------
@@ -130,15 +148,15 @@ def normal_explicit(alpha, sens, phi, masks):
 
 
 def normal_psi(alpha, sens, psi):
-    """Route (ii): N(alpha)_k = sum_c conj(S_c) F^H( sum_l Psi_kl F(S_c alpha_l) )."""
-    alpha = np.asarray(alpha, dtype=np.complex128)
-    sens = np.asarray(sens, dtype=np.complex128)
+    """Route (ii): N(alpha)_mk = sum_c conj(S_cm) F^H( sum_l Psi_kl F(sum_m' S_cm' alpha_m'l) )."""
+    alpha, sens, single = _maps(alpha, sens)
     out = np.zeros_like(alpha)
     for c in range(sens.shape[0]):
-        ks = fft2c(sens[c][None] * alpha)                       # [K, Ny, Nz]
-        mixed = np.einsum("klyz,lyz->kyz", psi, ks)
-        out += np.conj(sens[c])[None] * ifft2c(mixed)
-    return out
+        ks = fft2c(np.einsum("myz,mkyz->kyz", sens[c], alpha))  # [K, Ny, Nz]
+        mixed = ifft2c(np.einsum("klyz,lyz->kyz", psi, ks))
+        for m in range(sens.shape[1]):
+            out[m] += np.conj(sens[c, m])[None] * mixed
+    return out[0] if single else out
 
 
 # ---------------------------------------------------------------------------
@@ -153,56 +171,66 @@ def svt(X: np.ndarray, tau: float) -> np.ndarray:
     return (U * np.maximum(s - tau, 0.0)) @ Vh
 
 
+def block_ranges(n, b, s):
+    """Index sets of the blocks along one axis of length n: block p holds
+    (p*b + i + s) mod n for the i in [0, b) with p*b + i < n.  When b does not divide n
+    the last block is partial (n - (ceil(n/b) - 1) b entries); the paper's 260-point
+    axis with 12-point blocks has 21 full blocks and one of 8 (the paper does not say
+    how it treats the remainder)."""
+    return [(p * b + np.arange(min(b, n - p * b)) + s) % n for p in range((n + b - 1) // b)]
+
+
 def llr_prox(v, tau, shift, b):
     """Single-pass LLR prox: gather each shifted block, threshold, scatter back.
 
     Block (p, q) holds rows (p*b + i + s_y) mod Ny and columns (q*b + j + s_z) mod Nz,
-    i, j in [0, b); its B x K matrix has one row per voxel (row-major inside the
-    block) and one column per coefficient image.  Ny and Nz must be multiples of b.
+    i, j in [0, b) (partial blocks at the end of an axis b does not divide, see
+    ``block_ranges``); its matrix has one row per voxel (row-major inside the block)
+    and one column per coefficient image.
     """
     v = np.asarray(v, dtype=np.complex128)
+    if v.ndim == 4:   # one prox per map set (soft-SENSE): the blocks of each set's K images
+        return np.stack([llr_prox(vm, tau, shift, b) for vm in v])
     K, Ny, Nz = v.shape
     sy, sz = shift
-    if Ny % b or Nz % b:
-        raise ValueError("grid must be a multiple of the block size")
     out = np.empty_like(v)
-    for p in range(Ny // b):
-        rows = (p * b + np.arange(b) + sy) % Ny
-        for q in range(Nz // b):
-            cols = (q * b + np.arange(b) + sz) % Nz
-            blk = v[:, rows[:, None], cols[None, :]]           # [K, b, b]
-            X = blk.reshape(K, b * b).T                         # [B, K]
-            out[:, rows[:, None], cols[None, :]] = svt(X, tau).T.reshape(K, b, b)
+    for rows in block_ranges(Ny, b, sy):
+        for cols in block_ranges(Nz, b, sz):
+            blk = v[:, rows[:, None], cols[None, :]]           # [K, by, bz]
+            X = blk.reshape(K, -1).T                            # [by bz, K]
+            out[:, rows[:, None], cols[None, :]] = svt(X, tau).T.reshape(blk.shape)
     return out
 
 
 def llr_prox_explicit(v, tau, shift, b):
-    """The same prox written as: circular shift, extract non-overlapping blocks,
-    threshold, reassemble, shift back (the multi-pass form the paper replaced)."""
+    """The same prox written as: circular shift, cut the shifted images into
+    contiguous b x b tiles (the tiles of the last row / column cut short where b does
+    not divide the grid), threshold each, shift back (the multi-pass form the paper
+    replaced)."""
     v = np.asarray(v, dtype=np.complex128)
     K, Ny, Nz = v.shape
     sy, sz = shift
     w = np.roll(v, (-sy, -sz), axis=(1, 2))                     # w[i] = v[i + s]
-    blocks = w.reshape(K, Ny // b, b, Nz // b, b).transpose(1, 3, 2, 4, 0).reshape(Ny // b, Nz // b, b * b, K)
-    res = np.empty_like(blocks)
-    for p in range(Ny // b):
-        for q in range(Nz // b):
-            res[p, q] = svt(blocks[p, q], tau)
-    w2 = res.reshape(Ny // b, Nz // b, b, b, K).transpose(4, 0, 2, 1, 3).reshape(K, Ny, Nz)
-    return np.roll(w2, (sy, sz), axis=(1, 2))
+    res = np.empty_like(w)
+    for y0 in range(0, Ny, b):
+        for z0 in range(0, Nz, b):
+            tile = w[:, y0:y0 + b, z0:z0 + b]
+            X = tile.transpose(1, 2, 0).reshape(-1, K)           # voxels row-major, one column per image
+            res[:, y0:y0 + b, z0:z0 + b] = svt(X, tau).reshape(tile.shape[1], tile.shape[2], K).transpose(2, 0, 1)
+    return np.roll(res, (sy, sz), axis=(1, 2))
 
 
 def llr_value(alpha, shift, b):
     """sum over the shifted non-overlapping blocks of the nuclear norm (eq. llr, blocked form)."""
     alpha = np.asarray(alpha, dtype=np.complex128)
+    if alpha.ndim == 4:
+        return sum(llr_value(am, shift, b) for am in alpha)
     K, Ny, Nz = alpha.shape
     sy, sz = shift
     total = 0.0
-    for p in range(Ny // b):
-        rows = (p * b + np.arange(b) + sy) % Ny
-        for q in range(Nz // b):
-            cols = (q * b + np.arange(b) + sz) % Nz
-            X = alpha[:, rows[:, None], cols[None, :]].reshape(K, b * b).T
+    for rows in block_ranges(Ny, b, sy):
+        for cols in block_ranges(Nz, b, sz):
+            X = alpha[:, rows[:, None], cols[None, :]].reshape(K, -1).T
             total += np.linalg.svd(X, compute_uv=False).sum()
     return total
 
@@ -322,7 +350,8 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
     sens = np.asarray(sens, dtype=np.complex128)
     phi = np.asarray(phi, dtype=np.float64)
     K = phi.shape[1]
-    C, Ny, Nz = sens.shape
+    Ny, Nz = sens.shape[-2:]
+    shape = (K, Ny, Nz) if sens.ndim == 3 else (sens.shape[1], K, Ny, Nz)
     tau = lam / rho
     b0 = adjoint(samples, sens, phi, masks)
     b0_norm = np.linalg.norm(b0)
@@ -336,7 +365,7 @@ def admm(samples, sens, phi, masks, lam, rho, b, n_outer, n_cg, seed, g=0,
             return normal_explicit(v, sens, phi, masks) + rho * v
 
     if alpha0 is None:
-        alpha = np.zeros((K, Ny, Nz), dtype=np.complex128)
+        alpha = np.zeros(shape, dtype=np.complex128)
     else:
         alpha = np.array(alpha0, dtype=np.complex128, copy=True)
     z = alpha.copy()
@@ -475,13 +504,14 @@ def fista(samples, sens, phi, masks, lam, b, n_iter, shift=None, step=None, seed
     sens = np.asarray(sens, dtype=np.complex128)
     phi = np.asarray(phi, dtype=np.float64)
     K = phi.shape[1]
-    C, Ny, Nz = sens.shape
+    Ny, Nz = sens.shape[-2:]
+    shape = (K, Ny, Nz) if sens.ndim == 3 else (sens.shape[1], K, Ny, Nz)
     psi = space_time_kernel(phi, masks)
     aty = adjoint(samples, sens, phi, masks)
     if step is None:
-        v0 = np.random.default_rng(1).standard_normal((K, Ny, Nz)) + 0j
+        v0 = np.random.default_rng(1).standard_normal(shape) + 0j
         step = 1.0 / lipschitz(sens, psi, v0, 101)
-    x = np.zeros((K, Ny, Nz), dtype=np.complex128) if alpha0 is None else np.array(alpha0, dtype=np.complex128)
+    x = np.zeros(shape, dtype=np.complex128) if alpha0 is None else np.array(alpha0, dtype=np.complex128)
     yk = x.copy()
     t = 1.0
     for k in range(n_iter):

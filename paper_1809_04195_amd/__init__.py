@@ -73,6 +73,7 @@ class t2s_class(ctypes.Structure):
         ("ncoils", ctypes.c_int),
         ("nslices", ctypes.c_int),
         ("masks", ctypes.POINTER(ctypes.c_uint8)),
+        ("nmaps", ctypes.c_int),
     ]
 
 
@@ -246,14 +247,16 @@ def make_params(phi, lam, rho, block=8, n_outer=20, n_cg=5, tol=0.0, seed=0, fre
 
 
 def make_classes(classes):
-    """classes: list of (ny, nz, ncoils, nslices, masks uint8 [T, ny, nz])."""
+    """classes: list of (ny, nz, ncoils, nslices, masks uint8 [T, ny, nz][, nmaps])."""
     arr = (t2s_class * len(classes))()
     keep = []
-    for i, (ny, nz, nc, ns, masks) in enumerate(classes):
+    for i, cl in enumerate(classes):
+        ny, nz, nc, ns, masks = cl[:5]
+        nmaps = cl[5] if len(cl) > 5 else 1
         m = np.ascontiguousarray(masks, dtype=np.uint8)
         keep.append(m)
         arr[i] = t2s_class(ny=ny, nz=nz, ncoils=nc, nslices=ns,
-                           masks=m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+                           masks=m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), nmaps=nmaps)
     return arr, keep
 
 
@@ -401,7 +404,8 @@ class Plan:
         self.classes = classes
         self._params = make_params(self.phi, lam, rho, block, n_outer, n_cg, tol, seed, freeze_window,
                                    freeze_stall, check_every)
-        arr, self._keep = make_classes([(c["ny"], c["nz"], c["ncoils"], c["nslices"], c["masks"]) for c in classes])
+        arr, self._keep = make_classes([(c["ny"], c["nz"], c["ncoils"], c["nslices"], c["masks"], c.get("nmaps", 1))
+                                        for c in classes])
         self.handle = t2s_plan_create(self._params, arr, len(classes))
         self.nbytes = t2s_plan_workspace_bytes(self.handle)
         self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
@@ -432,13 +436,16 @@ class Plan:
         import torch
         ph = np.asarray(phi_te, dtype=np.float32).reshape(-1, self.K)
         c = self.classes[cls]
-        out = torch.empty((count, ph.shape[0], c["ny"], c["nz"]), dtype=torch.complex64, device="cuda")
+        M = c.get("nmaps", 1)
+        shape = (count, ph.shape[0], c["ny"], c["nz"]) if M <= 1 else (count, M, ph.shape[0], c["ny"], c["nz"])
+        out = torch.empty(shape, dtype=torch.complex64, device="cuda")
         t2s_backproject(self.handle, cls, first, count, ph, out, stream)
         return out
 
     def read(self, cls, first, count, which=T2S_ALPHA, device=False, stream=None):
         c = self.classes[cls]
-        shape = (count, self.K, c["ny"], c["nz"])
+        M = c.get("nmaps", 1)
+        shape = (count, self.K, c["ny"], c["nz"]) if M <= 1 else (count, M, self.K, c["ny"], c["nz"])
         if device:
             import torch
             out = torch.empty(shape, dtype=torch.complex64, device="cuda")

@@ -42,6 +42,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct ClassPlan {
     int ny = 0, nz = 0, C = 0, S = 0, P = 0, gbase = 0;
+    int M = 1;                              // coil-map sets (soft-SENSE)
     int nrw = 0, npb = 0, nllr = 0;
     std::vector<float> psi;                 // [K(K+1)/2][nz][ny] (host copy, documented layout)
     std::vector<float> psi_dev;             // pass-B order (see kernels.hpp)
@@ -60,7 +61,7 @@ struct ClassPlan {
 
 // Autotuned schedules, shared by every plan of the process, keyed by the shape of
 // the class and the device architecture.
-using SchedKey = std::tuple<int, int, int, int, int, std::string>;   // ny, nz, C, K, slices, arch
+using SchedKey = std::tuple<int, int, int, int, int, std::string>;   // ny, nz, C, M K, slices, arch
 struct Sched {
     int chunk, nstreams, order;
 };
@@ -123,7 +124,9 @@ void roots(int L, std::vector<float>& out) {
     }
 }
 
-size_t vec_bytes(const ClassPlan& c, int K) { return (size_t)c.S * K * c.ny * c.nz * 8; }
+// coefficient images per slice: K per coil-map set
+size_t vec_bytes(const ClassPlan& c, int K) { return (size_t)c.S * c.M * K * c.ny * c.nz * 8; }
+size_t slice_images(const ClassPlan& c, int K) { return (size_t)c.M * K * c.ny * c.nz; }
 
 void fill_args(t2s_plan* plan, ClassPlan& c) {
     char* b = plan->ws;
@@ -131,6 +134,7 @@ void fill_args(t2s_plan* plan, ClassPlan& c) {
     a.ny = c.ny;
     a.nz = c.nz;
     a.C = c.C;
+    a.M = c.M;
     a.K = plan->prm.K;
     a.T = plan->prm.T;
     a.P = c.P;
@@ -436,7 +440,8 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         return fail(T2S_ENONFINITE, "non-finite solver parameter");
     if (p->lambda < 0) return fail(T2S_EINVAL, "lambda must be >= 0");
     if (!(p->rho > 0)) return fail(T2S_EINVAL, "rho must be > 0");
-    if (p->block != 4 && p->block != 8 && p->block != 16) return fail(T2S_EINVAL, "block must be 4, 8 or 16");
+    if (p->block != 4 && p->block != 8 && p->block != 12 && p->block != 16)
+        return fail(T2S_EINVAL, "block must be 4, 8, 12 or 16");
     if (p->n_outer < 1 || p->n_cg < 1) return fail(T2S_EINVAL, "n_outer and n_cg must be >= 1");
     if (p->tol < 0) return fail(T2S_EINVAL, "tol must be >= 0");
     if (p->tol > 0 && (p->freeze_window < 1 || p->check_every < 1 || p->freeze_stall < 0 || p->freeze_stall >= 1))
@@ -448,9 +453,11 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         const t2s_class& c = classes[ci];
         if (!c.masks) return fail(T2S_EINVAL, "class " + std::to_string(ci) + ": masks is NULL");
         if (c.ncoils < 1 || c.nslices < 1) return fail(T2S_ESHAPE, "class " + std::to_string(ci) + ": ncoils and nslices must be >= 1");
-        if (c.ny < 16 || c.nz < 16 || c.ny % 16 || c.nz % 16 || c.ny % p->block || c.nz % p->block)
-            return fail(T2S_ESHAPE, "class " + std::to_string(ci) + ": ny, nz must be multiples of 16 and of block");
-        if (!t2s::fft_supported(c.ny) || !t2s::fft_supported(c.nz))
+        if (c.nmaps < 0 || c.nmaps > 2) return fail(T2S_ESHAPE, "class " + std::to_string(ci) + ": nmaps must be 0, 1 or 2");
+        if (c.ny < 16 || c.nz < 16 || c.ny % 16 || c.ny < p->block || c.nz < p->block)
+            return fail(T2S_ESHAPE, "class " + std::to_string(ci) +
+                                        ": ny must be a multiple of 16, ny and nz at least the block size");
+        if (!t2s::fft_col_supported(c.ny) || !t2s::fft_row_supported(c.nz))
             return fail(T2S_EUNSUPPORTED, "class " + std::to_string(ci) + ": no FFT plan for this grid length");
         const size_t tot = (size_t)T * c.ny * c.nz;
         for (size_t i = 0; i < tot; ++i)
@@ -470,6 +477,7 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.ny = src.ny;
         c.nz = src.nz;
         c.C = src.ncoils;
+        c.M = src.nmaps <= 1 ? 1 : src.nmaps;
         c.S = src.nslices;
         c.gbase = gbase;
         gbase += src.nslices;
@@ -527,7 +535,7 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.nrw = (ny / t2s::kRowTile) * K;
         const int wb = t2s::passB_columns(ny, K);
         c.npb = ((nz + wb - 1) / wb) * c.C;
-        c.nllr = t2s::llr_workgroups(ny, nz, p->block);
+        c.nllr = c.M * t2s::llr_workgroups(ny, nz, p->block);   // one run per map set
         c.loaded.assign(c.S, 0);
         c.outer_run.assign(c.S, 0);
         c.k_freeze.assign(c.S, -1);
@@ -550,10 +558,10 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.o_rowptr = take((N + 1) * 4);
         c.o_entt = take(c.ent_t.size() * 4);
         c.o_entp = take(c.ent_p.size() * 4);
-        c.o_sens = take((size_t)c.S * c.C * N * 8);
+        c.o_sens = take((size_t)c.S * c.C * c.M * N * 8);
         c.o_ksp = take((size_t)c.S * c.C * std::max(c.P, 1) * 8);
         for (int v = 0; v < 7; ++v) c.o_vec[v] = take(vec_bytes(c, K));
-        c.o_tmp = take((size_t)c.S * c.C * K * N * 8);
+        c.o_tmp = take((size_t)c.S * c.C * K * ((size_t)c.ny * ((c.nz + 15) & ~15)) * 8);   // 16-column tiles
         c.o_pa = take((size_t)c.S * c.nrw * 8);
         c.o_pb = take((size_t)c.S * c.npb * 8);
         c.o_rr = take((size_t)c.S * 2 * c.nrw * 8);
@@ -658,7 +666,7 @@ int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* s
     if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
     ClassPlan& c = plan->cls[cls];
     const size_t N = (size_t)c.ny * c.nz;
-    const size_t ns = (size_t)count * c.C * N * 2, nk = (size_t)count * c.C * c.P * 2;
+    const size_t ns = (size_t)count * c.C * c.M * N * 2, nk = (size_t)count * c.C * c.P * 2;
     if (mem == T2S_HOST) {
         const float* fs = (const float*)sens;
         const float* fk = (const float*)ksp;
@@ -670,7 +678,7 @@ int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* s
     hipStream_t st = (hipStream_t)stream;
     const hipMemcpyKind kind = mem == T2S_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const ClassArgs& a = c.args;
-    HIP_TRY(hipMemcpyAsync(a.sens + (size_t)first * c.C * N, sens, ns * 4, kind, st));
+    HIP_TRY(hipMemcpyAsync(a.sens + (size_t)first * c.C * c.M * N, sens, ns * 4, kind, st));
     if (nk) HIP_TRY(hipMemcpyAsync(a.ksp + (size_t)first * c.C * c.P, ksp, nk * 4, kind, st));
     HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st));
     {
@@ -695,7 +703,7 @@ int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* a
     for (int i = 0; i < count; ++i)
         if (!c.loaded[first + i]) return fail(T2S_ESTATE, "slice not loaded");
     const int K = plan->prm.K;
-    const size_t n = (size_t)count * K * c.ny * c.nz * 2;
+    const size_t n = (size_t)count * slice_images(c, K) * 2;
     if (mem == T2S_HOST) {
         const float* f = (const float*)alpha0;
         for (size_t i = 0; i < n; ++i)
@@ -704,7 +712,7 @@ int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* a
     hipStream_t st = (hipStream_t)stream;
     g_prof = &plan->prof;
     const ClassArgs& a = c.args;
-    float2* xs = a.x + (size_t)first * K * c.ny * c.nz;
+    float2* xs = a.x + (size_t)first * slice_images(c, K);
     HIP_TRY(hipMemcpyAsync(xs, alpha0, n * 4, mem == T2S_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
     HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st));
     // r = b0 + rho z - (A^H A + rho) alpha0 with z = alpha0, u = 0  =>  r = b0 - A^H A alpha0
@@ -886,7 +894,7 @@ int t2s_autotune(t2s_plan* plan, int reps, void* stream) {
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     for (ClassPlan& c : plan->cls) {
-        const SchedKey key{c.ny, c.nz, c.C, plan->prm.K, c.S, plan->arch};
+        const SchedKey key{c.ny, c.nz, c.C, c.M * plan->prm.K, c.S, plan->arch};
         {
             std::lock_guard<std::mutex> lk(g_sched_mu);
             auto it = g_sched.find(key);
@@ -966,7 +974,7 @@ int t2s_read_coeffs(t2s_plan* plan, int cls, int first, int count, void* out, in
         case T2S_RESIDUAL: src = a.r; break;
         default: return fail(T2S_EINVAL, "bad `which`");
     }
-    const size_t n = (size_t)plan->prm.K * c.ny * c.nz;
+    const size_t n = slice_images(c, plan->prm.K);
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(out, src + (size_t)first * n, (size_t)count * n * 8,
                            mem == T2S_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
@@ -1024,7 +1032,7 @@ int t2s_apply_llr(t2s_plan* plan, int cls, int first, int count, const void* in,
         if (shifts[2 * i] < 0 || shifts[2 * i] >= b || shifts[2 * i + 1] < 0 || shifts[2 * i + 1] >= b)
             return fail(T2S_EINVAL, "shift out of [0, block)");
     const ClassPlan& c = plan->cls[cls];
-    const size_t n = (size_t)plan->prm.K * c.ny * c.nz;
+    const size_t n = slice_images(c, plan->prm.K);
     hipStream_t st = (hipStream_t)stream;
     for (int i = 0; i < count; ++i)
         HIP_CHECK_LAUNCH(t2s::launch_llr(c.args, first + i, 1, t2s::kLlrProx, 0, (const float2*)in + i * n,
@@ -1041,7 +1049,7 @@ int t2s_lipschitz(t2s_plan* plan, int cls, int iters, double* L, void* stream) {
     for (int s = 0; s < c.S; ++s)
         if (!c.loaded[s]) return fail(T2S_ESTATE, "not every slice of the class is loaded");
     const ClassArgs& a = c.args;
-    const size_t n = (size_t)plan->prm.K * c.ny * c.nz;
+    const size_t n = slice_images(c, plan->prm.K);
     hipStream_t st = (hipStream_t)stream;
     g_prof = &plan->prof;
     HIP_CHECK_LAUNCH(t2s::launch_set_state(a, 0, c.S, 1, -1, -1, st));
@@ -1092,7 +1100,7 @@ int t2s_fista(t2s_plan* plan, int mode, int n_iter, float step, void* stream) {
     for (ClassPlan& c : plan->cls) {
         // every slice active, no frozen shift, iteration counter 0; momentum point y = x
         HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, 0, st));
-        const size_t n = (size_t)plan->prm.K * c.ny * c.nz;
+        const size_t n = slice_images(c, plan->prm.K);
         HIP_TRY(hipMemcpyAsync(c.args.z, c.args.x, (size_t)c.S * n * 8, hipMemcpyDeviceToDevice, st));
     }
     auto step_range = [&](const ClassArgs& a, int s0, int count) -> int {
@@ -1125,7 +1133,7 @@ int t2s_fista(t2s_plan* plan, int mode, int n_iter, float step, void* stream) {
 }
 
 int t2s_readout_ifft(int nx, int ncoils, int nsamples, const void* in, void* out, void* stream) {
-    if (!t2s::fft_supported(nx)) return fail(T2S_ESHAPE, "unsupported readout length " + std::to_string(nx));
+    if (!t2s::fft_col_supported(nx)) return fail(T2S_ESHAPE, "unsupported readout length " + std::to_string(nx));
     if (ncoils < 1 || ncoils > 65535) return fail(T2S_ESHAPE, "ncoils must be in [1, 65535]");
     if (nsamples < 0) return fail(T2S_ESHAPE, "nsamples must be >= 0");
     if (nsamples == 0) return 0;   // nothing to transform (empty arrays may come as NULL)

@@ -1,17 +1,12 @@
 // fft.hpp -- mixed-radix complex FFT building blocks for gfx950 (also compilable
-// as plain C++ so the index arithmetic and the codelets can be checked on a CPU).
+// as plain C++ so the codelets and the two-step plans can be checked on a CPU).
 //
 // Transforms are unnormalised: forward X[k] = sum_n x[n] W_L^{nk}, W_L = exp(-2 pi i / L);
-// inverse uses W_L^{-nk}.  A length-L transform is a sequence of radix-R Stockham
-// passes (R from the plan of L).  Pass p with stride NS (product of the earlier
-// radices) does, for every butterfly j in [0, L/R):
-//     v[r]  = x[j + r L/R]                      r = 0..R-1
-//     v[r] *= W_{NS R}^{r (j mod NS)}            (skipped when NS == 1)
-//     v     = DFT_R(v)
-//     y[(j / NS) NS R + (j mod NS) + r NS] = v[r]
-// which leaves the result in natural order after the last pass.  Small DFTs run
-// in registers (radix 2/3/4/5 codelets composed by Cooley-Tukey with compile-time
-// twiddles); the inter-pass twiddles W_L^m come from a table (LDS on the GPU).
+// inverse uses W_L^{-nk}.  Small DFTs run in registers: radix 2/3/4/5 codelets, odd
+// prime radices (13) by the symmetric direct sum, composites by Cooley-Tukey, all with
+// compile-time twiddles; a length-L transform is a two-step plan L = R1 R2 across the
+// threads of one transform with one LDS exchange (RegPlan / RowPlan below), with the
+// inter-step twiddles W_L^m from a table (LDS on the GPU).
 #pragma once
 
 #if defined(__HIPCC__)
@@ -178,6 +173,39 @@ T2S_HD T2S_INL void dft_base(float2 (&v)[R]) {
         v[4] = cadd(m1, mul_plus_i(n1));
         v[2] = cadd(m2, mul_minus_i(n2));
         v[3] = cadd(m2, mul_plus_i(n2));
+    } else {
+        // odd prime R >= 7: with a_n = x_n + x_(R-n), b_n = x_n - x_(R-n) (n = 1..(R-1)/2),
+        // X_k = x_0 + sum_n a_n cos(2 pi n k / R) - i sum_n b_n sin(2 pi n k / R) and
+        // X_(R-k) the same with +i
+        static_assert(R % 2 == 1, "direct codelet for odd radices only");
+        constexpr int H = (R - 1) / 2;
+        constexpr RootTable<R> T{};   // T.re = cos, T.im = -sin of 2 pi m / R
+        float2 a[H + 1], b[H + 1];
+#pragma unroll
+        for (int n = 1; n <= H; ++n) {
+            a[n] = cadd(v[n], v[R - n]);
+            b[n] = csub(v[n], v[R - n]);
+        }
+        float2 X[R];
+        float2 s0 = v[0];
+#pragma unroll
+        for (int n = 1; n <= H; ++n) s0 = cadd(s0, a[n]);
+        X[0] = s0;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            float2 A = v[0], Bs = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int n = 1; n <= H; ++n) {
+                const int e = (n * k) % R;
+                const float c = T.re[e], sn = -T.im[e];
+                A = make_float2(A.x + c * a[n].x, A.y + c * a[n].y);
+                Bs = make_float2(Bs.x + sn * b[n].x, Bs.y + sn * b[n].y);
+            }
+            X[k] = cadd(A, mul_minus_i(Bs));
+            X[R - k] = cadd(A, mul_plus_i(Bs));
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = X[r];
     }
 }
 
@@ -225,98 +253,14 @@ T2S_HD T2S_INL void dft_dir(float2 (&v)[R]) {
 }
 
 // ---------------------------------------------------------------------------
-// radix plans: L = R1 * R2 (* R3)
+// supported lengths: a column length (passes B and the readout transform, whose
+// thread layout needs R2 | 16 and ny a multiple of 16) or a row length (passes A and C)
 // ---------------------------------------------------------------------------
-template <int... Rs>
-struct Radices {};
-
-template <int L>
-struct FftPlan;
-template <> struct FftPlan<16> { using type = Radices<4, 4>; };
-template <> struct FftPlan<32> { using type = Radices<8, 4>; };
-template <> struct FftPlan<48> { using type = Radices<16, 3>; };
-template <> struct FftPlan<64> { using type = Radices<8, 8>; };
-template <> struct FftPlan<96> { using type = Radices<16, 6>; };
-template <> struct FftPlan<128> { using type = Radices<16, 8>; };
-template <> struct FftPlan<160> { using type = Radices<16, 10>; };
-template <> struct FftPlan<192> { using type = Radices<16, 12>; };
-template <> struct FftPlan<256> { using type = Radices<16, 16>; };
-template <> struct FftPlan<320> { using type = Radices<16, 20>; };
-template <> struct FftPlan<384> { using type = Radices<16, 24>; };
-template <> struct FftPlan<512> { using type = Radices<16, 32>; };
-
-constexpr bool fft_length_supported(int L) {
+constexpr bool fft_col_length_supported(int L) {
     return L == 16 || L == 32 || L == 48 || L == 64 || L == 96 || L == 128 || L == 160 || L == 192 ||
-           L == 256 || L == 320 || L == 384 || L == 512;
+           L == 240 || L == 256 || L == 320 || L == 384 || L == 512;
 }
-
-// padded LDS position of element i of a transform (one spare slot per 16)
-T2S_HD T2S_INL int ph(int i) { return i + (i >> 4); }
-// LDS stride between transforms of length L (odd, so rows start on different banks)
-constexpr int lds_ld(int L) { return (L + L / 16) | 1; }
-
-// one Stockham pass for the items [tid, ntr * L / R) step nthr
-template <int L, int R, int NS, bool INV>
-T2S_HD T2S_INL void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst, int ntr, int ld,
-                                  const float2* __restrict__ tw, int tid, int nthr) {
-    constexpr int NB = L / R;
-    for (int it = tid; it < ntr * NB; it += nthr) {
-        const int t = it / NB;
-        const int j = it - t * NB;
-        const float2* s = src + t * ld;
-        float2 v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = s[ph(j + r * NB)];
-        if constexpr (NS > 1) {
-            const int k = j % NS;
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = tw[(r * k * (L / (NS * R))) % L];
-                if (INV) w.y = -w.y;
-                v[r] = cmul(v[r], w);
-            }
-        }
-        dft_dir<R, INV>(v);
-        const int base = (j / NS) * NS * R + (j % NS);
-        float2* d = dst + t * ld;
-#pragma unroll
-        for (int r = 0; r < R; ++r) d[ph(base + r * NS)] = v[r];
-    }
-}
-
-template <typename P>
-struct PassCount;
-template <int... Rs>
-struct PassCount<Radices<Rs...>> {
-    static constexpr int value = sizeof...(Rs);
-};
-
-template <int L>
-constexpr int fft_passes() {
-    return PassCount<typename FftPlan<L>::type>::value;
-}
-
-// Host-side sequential emulation of the LDS FFT (all "threads" of a pass, then the
-// next pass): the same pass code as the device path, used by CPU tests.
-template <int L, int NS, bool INV, int R, int... Rest>
-T2S_INL float2* fft_emulate_passes(float2* a, float2* b, int ntr, int ld, const float2* tw) {
-    stockham_pass<L, R, NS, INV>(a, b, ntr, ld, tw, 0, 1);
-    if constexpr (sizeof...(Rest) > 0) {
-        return fft_emulate_passes<L, NS * R, INV, Rest...>(b, a, ntr, ld, tw);
-    } else {
-        return b;
-    }
-}
-
-template <int L, bool INV, int... Rs>
-T2S_INL float2* fft_emulate_unpack(Radices<Rs...>, float2* a, float2* b, int ntr, int ld, const float2* tw) {
-    return fft_emulate_passes<L, 1, INV, Rs...>(a, b, ntr, ld, tw);
-}
-
-template <int L, bool INV>
-T2S_INL float2* fft_emulate(float2* a, float2* b, int ntr, int ld, const float2* tw) {
-    return fft_emulate_unpack<L, INV>(typename FftPlan<L>::type{}, a, b, ntr, ld, tw);
-}
+constexpr bool fft_row_length_supported(int L) { return fft_col_length_supported(L) || L == 260; }
 
 // ---------------------------------------------------------------------------
 // Two-step ("four-step") register plans: L = R1 * R2.
@@ -342,6 +286,7 @@ template <> struct RegPlan<96> { static constexpr int R1 = 12, R2 = 8; };
 template <> struct RegPlan<128> { static constexpr int R1 = 8, R2 = 16; };
 template <> struct RegPlan<160> { static constexpr int R1 = 10, R2 = 16; };
 template <> struct RegPlan<192> { static constexpr int R1 = 12, R2 = 16; };
+template <> struct RegPlan<240> { static constexpr int R1 = 15, R2 = 16; };
 template <> struct RegPlan<256> { static constexpr int R1 = 16, R2 = 16; };
 template <> struct RegPlan<320> { static constexpr int R1 = 20, R2 = 16; };
 template <> struct RegPlan<384> { static constexpr int R1 = 24, R2 = 16; };
@@ -354,6 +299,8 @@ template <> struct RegPlan<512> { static constexpr int R1 = 32, R2 = 16; };
 template <int L>
 struct RowPlan : RegPlan<L> {};
 template <> struct RowPlan<384> { static constexpr int R1 = 16, R2 = 24; };
+// 260 = 13 x 20 (radix-13 codelet), a row length only (260 is not a multiple of 16)
+template <> struct RowPlan<260> { static constexpr int R1 = 13, R2 = 20; };
 
 template <int L, class Plan = RegPlan<L>>
 struct RegGeom {
@@ -367,30 +314,5 @@ struct RegGeom {
     static constexpr int TB = TB0 + ((17 - TB0 % 16) % 16);   // per-transform LDS words, == 1 mod 16
 };
 
-#if defined(__HIPCC__)
-// Device LDS FFT of ntr transforms, all threads of the workgroup taking part.
-// Input in `a` (padded layout); returns the buffer (a or b) that holds the result.
-// Ends with a barrier, so the result can be read by any thread.
-template <int L, int NS, bool INV, int R, int... Rest>
-__device__ T2S_INL float2* fft_lds_passes(float2* a, float2* b, int ntr, int ld, const float2* tw) {
-    stockham_pass<L, R, NS, INV>(a, b, ntr, ld, tw, threadIdx.x, blockDim.x);
-    __syncthreads();
-    if constexpr (sizeof...(Rest) > 0) {
-        return fft_lds_passes<L, NS * R, INV, Rest...>(b, a, ntr, ld, tw);
-    } else {
-        return b;
-    }
-}
-
-template <int L, bool INV, int... Rs>
-__device__ T2S_INL float2* fft_lds_unpack(Radices<Rs...>, float2* a, float2* b, int ntr, int ld, const float2* tw) {
-    return fft_lds_passes<L, 1, INV, Rs...>(a, b, ntr, ld, tw);
-}
-
-template <int L, bool INV>
-__device__ T2S_INL float2* fft_lds(float2* a, float2* b, int ntr, int ld, const float2* tw) {
-    return fft_lds_unpack<L, INV>(typename FftPlan<L>::type{}, a, b, ntr, ld, tw);
-}
-#endif
 
 }  // namespace t2s

@@ -104,6 +104,8 @@ __device__ __forceinline__ Blk block_coords(bool grouped) {
 __device__ __forceinline__ size_t tile_col(int z, int ny) { return (size_t)(z >> 4) * (ny >> 4) * 256 + ((z & 15) << 4); }
 __device__ __forceinline__ int tile_row(int y) { return ((y >> 4) << 8) + (y & 15); }
 __device__ __forceinline__ size_t tix(int y, int z, int ny) { return tile_col(z, ny) + tile_row(y); }
+// elements of one tiled image: nz rounded up to whole 16-column tiles (ny is a multiple of 16)
+__host__ __device__ __forceinline__ size_t tmp_image(int ny, int nz) { return (size_t)ny * ((nz + 15) & ~15); }
 
 // The pass intermediate is streamed: each pass reads or writes every element once and
 // the next pass finds it in HBM, not in cache (a class's intermediate is gigabytes).
@@ -201,7 +203,8 @@ template <int R1, int R2>
 __device__ __forceinline__ double cg_row_update(const float2 (&acc)[R1], const float2* __restrict__ p,
                                                 float2* __restrict__ x, float2* __restrict__ r, float rho,
                                                 float alpha) {
-    constexpr int H = R1 >= 8 ? R1 / 2 : R1;
+    constexpr int H = (R1 >= 8 && R1 % 2 == 0) ? R1 / 2 : R1;   // odd R1 (13, 15): one pass
+    static_assert(R1 % H == 0, "the halves must tile the row");
     double dot = 0.0;
 #pragma unroll
     for (int h = 0; h < R1; h += H) {
@@ -235,7 +238,10 @@ __device__ __forceinline__ double cg_row_update(const float2 (&acc)[R1], const f
 // mappings meet at the LDS exchange: row-major lanes for the coalesced row loads,
 // row-fastest lanes for the stores (a wave writes one 512-byte run of a tile).
 // ---------------------------------------------------------------------------
-template <int L>
+// M: coil-map sets (soft-SENSE, Sec. II-A): coil c sees sum_m S_(c,m) p_(m,k); the
+// coefficient vectors hold M K images per slice ([M][K][ny][nz]), the maps C M per
+// slice ([C][M][ny][nz])
+template <int L, int M>
 __global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_eu(1, passA_waves<L>())))
 void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
                                                               int src_s0, int first, PartialSrc gc, PartialSrc gp,
@@ -254,6 +260,7 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
     const int y0 = bk.x * RT;
     const int ny = a.ny;
     const size_t N = (size_t)ny * L;
+    const size_t NTI = tmp_image(ny, L);
     const int tid = threadIdx.x;
     for (int i = tid; i < L; i += NT) tw[i] = a.twz[i];
 
@@ -268,11 +275,15 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
         beta = g0 > 0.0 ? (float)(g1 / g0) : 0.0f;
     }
     const size_t rowoff = (size_t)(y0 + r1) * L;
-    float2 pv[R1];
+    const int KM = M * a.K;
+    float2 pv[M][R1];
     double pp = 0.0;
-    if (on1)
-        pp = direction_update<R1, R2>(src + ((size_t)(s - src_s0) * a.K + k) * N + rowoff,
-                                      a.p + ((size_t)s * a.K + k) * N + rowoff, t1, first, beta, pv);
+    if (on1) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            pp += direction_update<R1, R2>(src + ((size_t)(s - src_s0) * KM + m * a.K + k) * N + rowoff,
+                                           a.p + ((size_t)s * KM + m * a.K + k) * N + rowoff, t1, first, beta, pv[m]);
+    }
     if (want_pp) {
         const double tot = block_sum(pp, red);
         if (tid == 0) a.pa[(size_t)s * a.nrw + bk.y * gridDim.x + bk.x] = tot;
@@ -280,17 +291,46 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
     __syncthreads();
     float2* xr1 = xb + r1 * TB;
     const float2* xr3 = xb + r3 * TB;
+    // the next coil's map row is loaded while the current one is transformed (up to 24
+    // values per thread; 32 at 512 points leave no registers for it)
+    constexpr bool kPrefetch = M == 1 && R1 <= 24;
+    const float2* S0 = a.sens + (size_t)s * a.C * M * N + rowoff + t1;
+    float2 sn[R1];
+    if (on1 && kPrefetch) {
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) sn[n1] = S0[R2 * n1];
+    }
     for (int c = 0; c < a.C; ++c) {
         if (on1) {
-            const float2* S = a.sens + ((size_t)s * a.C + c) * N + rowoff;
             float2 v[R1];
+            if constexpr (kPrefetch) {
 #pragma unroll
-            for (int n1 = 0; n1 < R1; ++n1) v[n1] = S[R2 * n1 + t1];
-            // all of the coil's loads in flight before the first use (the scheduler would
-            // otherwise interleave load / wait / multiply to save registers)
-            __builtin_amdgcn_sched_barrier(0);
+                for (int n1 = 0; n1 < R1; ++n1) v[n1] = sn[n1];
+                if (c + 1 < a.C) {
+                    const float2* S = S0 + (size_t)(c + 1) * N;
 #pragma unroll
-            for (int n1 = 0; n1 < R1; ++n1) v[n1] = cmul(v[n1], pv[n1]);
+                    for (int n1 = 0; n1 < R1; ++n1) sn[n1] = S[R2 * n1];
+                }
+                // all of the next coil's loads in flight before the first use (the
+                // scheduler would otherwise interleave load / wait / multiply)
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int n1 = 0; n1 < R1; ++n1) v[n1] = cmul(v[n1], pv[0][n1]);
+            } else {
+                // sum over the map sets of S_(c,m) p_(m,k)
+#pragma unroll
+                for (int n1 = 0; n1 < R1; ++n1) v[n1] = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const float2* S = S0 + ((size_t)c * M + m) * N;
+                    float2 sm[R1];
+#pragma unroll
+                    for (int n1 = 0; n1 < R1; ++n1) sm[n1] = S[R2 * n1];
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int n1 = 0; n1 < R1; ++n1) v[n1] = cadd(v[n1], cmul(sm[n1], pv[m][n1]));
+                }
+            }
             dft_dir<R1, false>(v);
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) xr1[k1 * (R2 + 1) + t1] = tw_mul<false>(v[k1], tw, t1 * k1);
@@ -301,7 +341,7 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
 #pragma unroll
             for (int n2 = 0; n2 < R2; ++n2) b[n2] = xr3[t3 * (R2 + 1) + n2];
             dft_dir<R2, false>(b);
-            float2* out = a.tmp + (((size_t)s * a.C + c) * a.K + k) * N + tile_row(y0 + r3);
+            float2* out = a.tmp + (((size_t)s * a.C + c) * a.K + k) * NTI + tile_row(y0 + r3);
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2) st_stream<true>(&out[tile_col(t3 + R1 * k2, ny)], b[k2]);
         }
@@ -326,15 +366,23 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
     __shared__ float2 tw[L];
     __shared__ float2 xb[W * TB];
 
-    const int s = s0 + blockIdx.z;
+    // A table larger than 2 MB does not stay in an XCD's L2 while the pass streams: the
+    // workgroups then go coil fastest, each XCD a contiguous run of (slice, column
+    // tile), so the C workgroups that read the same columns of the table run back to
+    // back on one XCD and share them through its L2 (the 384 x 384, K = 5 table is
+    // 9.4 MB; dealt round-robin, every coil re-read it from the Infinity Cache and the
+    // pass fetched 2.6x its algorithmic bytes)
+    constexpr int KPB = (K * (K + 1) / 2 + 3) / 4 * 16;   // table bytes per frequency
+    const Blk bk = block_coords((size_t)a.nz * L * KPB > (2u << 20));
+    const int s = s0 + bk.z;
     if (!slice_active(a, s)) return;
-    const int c = blockIdx.y;
+    const int c = bk.y;
     const int tid = threadIdx.x;
     const int w = tid / P, t = tid - w * P;
     const int nz = a.nz;
-    const int z = blockIdx.x * W + w;
+    const int z = bk.x * W + w;
     const bool colok = z < nz;
-    const size_t N = (size_t)L * nz;
+    const size_t N = tmp_image(L, nz);   // image stride of the tiled intermediate
     for (int i = tid; i < L; i += NT) tw[i] = a.twy[i];
     __syncthreads();
     // columns past nz (last tile) read column 0 and are never stored: no selects between
@@ -443,7 +491,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
         // exchange buffer is free after the last transform and holds the partials
         static_assert(W * TB * sizeof(float2) >= NT * sizeof(double), "exchange buffer too small");
         const double tot = block_sum_ragged(quad, reinterpret_cast<double*>(xb));
-        if (tid == 0) a.pb[(size_t)s * a.npb + c * gridDim.x + blockIdx.x] = tot;
+        if (tid == 0) a.pb[(size_t)s * a.npb + c * gridDim.x + bk.x] = tot;
     }
 }
 
@@ -462,7 +510,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
     const int nz = a.nz;
     const int z = blockIdx.x * W + w;
     const bool colok = z < nz;
-    const size_t N = (size_t)L * nz;
+    const size_t N = tmp_image(L, nz);   // image stride of the tiled intermediate
     for (int i = tid; i < L; i += NT) tw[i] = a.twy[i];
     __syncthreads();
     float2* col = a.tmp + ((size_t)s * a.C + c) * (size_t)a.K * N + tile_col(colok ? z : 0, L);
@@ -498,7 +546,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
 // out = acc + rho_add p (MODE 0), out = acc (MODE 1), or the CG step (MODE 2):
 // w = acc + rho p, a = gamma / <p, M p>, x += a p, r -= a w, partial <r, r>.
 // ---------------------------------------------------------------------------
-template <int L, int MODE>
+template <int L, int MODE, int M>
 __global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_eu(1, kPassCWavesPerSimd)))
 void k_passC(ClassArgs a, int s0, float rho_add,
                                                               float2* __restrict__ outp, int out_s0, PartialSrc gc,
@@ -517,6 +565,7 @@ void k_passC(ClassArgs a, int s0, float rho_add,
     const int y0 = bk.x * RT;
     const int ny = a.ny;
     const size_t N = (size_t)ny * L;
+    const size_t NTI = tmp_image(ny, L);
     const int tid = threadIdx.x;
     for (int i = tid; i < L; i += NT) tw[i] = a.twz[i];
     __syncthreads();
@@ -529,12 +578,15 @@ void k_passC(ClassArgs a, int s0, float rho_add,
     float2* xr1 = xb + r1 * TB;
     float2* xr3 = xb + r3 * TB;
 
-    float2 acc[R1];
+    const int KM = M * a.K;
+    float2 acc[M][R1];
 #pragma unroll
-    for (int i = 0; i < R1; ++i) acc[i] = make_float2(0.f, 0.f);
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int i = 0; i < R1; ++i) acc[m][i] = make_float2(0.f, 0.f);
     // spectra of the next coil are loaded while the current one is transformed
-    const float2* T0 = a.tmp + ((size_t)s * a.C * a.K + k) * N + tile_row(y0 + r3);
-    const size_t cstride = (size_t)a.K * N;
+    const float2* T0 = a.tmp + ((size_t)s * a.C * a.K + k) * NTI + tile_row(y0 + r3);
+    const size_t cstride = (size_t)a.K * NTI;
     float2 nb[R2];
     if (on3) {
 #pragma unroll
@@ -556,8 +608,8 @@ void k_passC(ClassArgs a, int s0, float rho_add,
         }
         __syncthreads();
         if (on1) {
-            const float2* S = a.sens + ((size_t)s * a.C + c) * N + rowoff;
-            if constexpr (R1 <= 24) {
+            const float2* S = a.sens + ((size_t)s * a.C + c) * M * N + rowoff;
+            if constexpr (M == 1 && R1 <= 24) {
                 // the coil's map is loaded first, in flight during the LDS reads and the
                 // FFT (R1 = 32 has no registers to spare for it)
                 float2 sv[R1];
@@ -569,14 +621,18 @@ void k_passC(ClassArgs a, int s0, float rho_add,
                 for (int k1 = 0; k1 < R1; ++k1) v[k1] = xr1[t1 * (R1 + 1) + k1];
                 dft_dir<R1, true>(v);
 #pragma unroll
-                for (int m2 = 0; m2 < R1; ++m2) acc[m2] = cadd(acc[m2], cmulc(v[m2], sv[m2]));
+                for (int m2 = 0; m2 < R1; ++m2) acc[0][m2] = cadd(acc[0][m2], cmulc(v[m2], sv[m2]));
             } else {
                 float2 v[R1];
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) v[k1] = xr1[t1 * (R1 + 1) + k1];
                 dft_dir<R1, true>(v);
+                // every map set combines the same coil image: acc_m += conj(S_(c,m)) (.)
 #pragma unroll
-                for (int m2 = 0; m2 < R1; ++m2) acc[m2] = cadd(acc[m2], cmulc(v[m2], S[t1 + R2 * m2]));
+                for (int m = 0; m < M; ++m)
+#pragma unroll
+                    for (int m2 = 0; m2 < R1; ++m2)
+                        acc[m][m2] = cadd(acc[m][m2], cmulc(v[m2], S[(size_t)m * N + t1 + R2 * m2]));
             }
         }
         __syncthreads();
@@ -587,24 +643,32 @@ void k_passC(ClassArgs a, int s0, float rho_add,
         const double pmp = partial_sum(PartialSrc{a.pb, a.npb, a.npb}, s) +
                            (double)a.rho * partial_sum(PartialSrc{a.pa, a.nrw, a.nrw}, s);
         const float alpha = (gamma > 0.0 && pmp > 0.0) ? (float)(gamma / pmp) : 0.0f;
-        const size_t vo = ((size_t)s * a.K + k) * N + rowoff + t1;
         double dot = 0.0;
-        if (on1) dot = cg_row_update<R1, R2>(acc, a.p + vo, a.x + vo, a.r + vo, a.rho, alpha);
+        if (on1) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const size_t vo = ((size_t)s * KM + m * a.K + k) * N + rowoff + t1;
+                dot += cg_row_update<R1, R2>(acc[m], a.p + vo, a.x + vo, a.r + vo, a.rho, alpha);
+            }
+        }
         const double tot = block_sum(dot, red);
         if (tid == 0) a.rr[((size_t)s * 2 + out_buf) * a.nrw + bk.y * gridDim.x + bk.x] = tot;
     } else {
-        float2* out = outp + ((size_t)(s - out_s0) * a.K + k) * N + rowoff;
         if (on1) {
-            const float2* pp = a.p + ((size_t)s * a.K + k) * N + rowoff;
 #pragma unroll
-            for (int m2 = 0; m2 < R1; ++m2) {
-                const int pos = t1 + R2 * m2;
-                float2 w = acc[m2];
-                if constexpr (MODE == 0) {
-                    const float2 pv = pp[pos];
-                    w = make_float2(w.x + rho_add * pv.x, w.y + rho_add * pv.y);
+            for (int m = 0; m < M; ++m) {
+                float2* out = outp + ((size_t)(s - out_s0) * KM + m * a.K + k) * N + rowoff;
+                const float2* pp = a.p + ((size_t)s * KM + m * a.K + k) * N + rowoff;
+#pragma unroll
+                for (int m2 = 0; m2 < R1; ++m2) {
+                    const int pos = t1 + R2 * m2;
+                    float2 w = acc[m][m2];
+                    if constexpr (MODE == 0) {
+                        const float2 pv = pp[pos];
+                        w = make_float2(w.x + rho_add * pv.x, w.y + rho_add * pv.y);
+                    }
+                    out[pos] = w;
                 }
-                out[pos] = w;
             }
         }
     }
@@ -641,10 +705,11 @@ __global__ __launch_bounds__(kThreads) void k_project(ClassArgs a, int s0) {
     }
     const int yp = q % ny, zp = q / ny;
     const float sc = (((yp + zp) & 1) ? -1.0f : 1.0f) / sqrtf((float)N);
-    float2* out = a.tmp + ((size_t)s * a.C + c) * K * (size_t)N + tix(yp, zp, ny);
+    const size_t NTI = tmp_image(ny, nz);
+    float2* out = a.tmp + ((size_t)s * a.C + c) * K * NTI + tix(yp, zp, ny);
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
-        if (k < K) out[(size_t)k * N] = cscale(acc[k], sc);
+        if (k < K) out[(size_t)k * NTI] = cscale(acc[k], sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -653,7 +718,7 @@ __global__ __launch_bounds__(kThreads) void k_project(ClassArgs a, int s0) {
 __global__ __launch_bounds__(kThreads) void k_init(ClassArgs a, int s0, const float2* __restrict__ alpha0, int sub_w) {
     __shared__ double red[kThreads / 64];
     const int s = s0 + blockIdx.z;
-    const size_t n = (size_t)a.K * a.ny * a.nz;
+    const size_t n = (size_t)a.M * a.K * a.ny * a.nz;
     const size_t base = (size_t)s * n;
     const float2* a0 = alpha0 ? alpha0 + (size_t)(s - s0) * n : nullptr;
     double dot = 0.0, bb = 0.0;
@@ -748,6 +813,8 @@ __device__ __forceinline__ float2 fista_point(const ClassArgs& a, size_t i, floa
     return make_float2(y.x - step * g.x, y.y - step * g.y);
 }
 
+constexpr int pow2_at_least(int b) { return b <= 1 ? 1 : 2 * pow2_at_least((b + 1) / 2); }
+
 // MODE kLlrAdmm: z = SVT(x + u) with the ADMM u and right-hand-side updates.
 // MODE kLlrProx: out = SVT(in) at an explicit shift.
 // MODE kLlrFista: x_new = SVT(y - step (A^H A y - b0)), the next momentum point
@@ -764,9 +831,18 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
     const int ny = a.ny, nz = a.nz;
     const size_t N = (size_t)ny * nz;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nsz = (nz + 63) / 64;
-    const int nstrips = (ny / B) * nsz;
-    const int st = blockIdx.x * (kThreads / 64) + wave;
+    // a wave holds BW blocks side by side, GW lanes each (B of them active: one lane per
+    // block column); the last block row / column is partial when B does not divide the
+    // grid
+    constexpr int GW = pow2_at_least(B), BW = 64 / GW;
+    const int nby = (ny + B - 1) / B, nbz = (nz + B - 1) / B;
+    const int nsz = (nbz + BW - 1) / BW;
+    const int nstrips = nby * nsz;
+    // every map set (soft-SENSE) has its own blocks of its K images: the a.nllr
+    // workgroups of a slice are a.M runs of nllr / M
+    const int wpm = a.nllr / a.M;
+    const int mset = blockIdx.x / wpm;
+    const int st = (blockIdx.x - mset * wpm) * (kThreads / 64) + wave;
 
     int sy = sy_arg, sz = sz_arg;
     if (kState) {
@@ -778,7 +854,7 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
         sy = (int)((h & 0xFFFFFFFFull) % (uint64_t)B);
         sz = (int)((h >> 32) % (uint64_t)B);
     }
-    const size_t vb = (size_t)(kState ? s : s - s0) * K * N;
+    const size_t vb = ((size_t)(kState ? s : s - s0) * a.M + mset) * K * N;
     float mom = 0.0f;
     if (MODE == kLlrFista) {
         const int kk = a.state[4 * s + 2];
@@ -788,9 +864,11 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
     }
     const bool valid = st < nstrips;
     const int prow = valid ? st / nsz : 0;
-    const int col = (valid ? (st % nsz) : 0) * 64 + lane;
-    const bool act = valid && col < nz;
+    const int jl = lane % GW;
+    const int col = ((valid ? (st % nsz) : 0) * BW + lane / GW) * B + jl;
+    const bool act = valid && jl < B && col < nz;
     const int zc = (col + sz) % nz;
+    const int nrows = min(B, ny - prow * B);   // rows of this block row (partial at the end)
 
     // ---- Gram matrix of this lane's block (FP64) ----
     cd2 G[K][K];
@@ -800,6 +878,7 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
         for (int l = 0; l < K; ++l) G[k][l] = cd2{0.0, 0.0};
     if (act) {
         for (int i = 0; i < B; ++i) {
+            if (i >= nrows) break;
             const int yr = (prow * B + i + sy) % ny;
             const size_t idx = (size_t)yr * nz + zc;
             float2 v[K];
@@ -824,7 +903,7 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
 #pragma unroll
         for (int l = k; l < K; ++l) {
 #pragma unroll
-            for (int o = 1; o < B; o <<= 1) {
+            for (int o = 1; o < GW; o <<= 1) {
                 G[k][l].x += __shfl_xor(G[k][l].x, o);
                 G[k][l].y += __shfl_xor(G[k][l].y, o);
             }
@@ -863,6 +942,7 @@ __global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int koute
     double s_az = 0.0, s_zz = 0.0, s_a = 0.0, s_z = 0.0, s_u = 0.0, s_r = 0.0;
     if (act) {
         for (int i = 0; i < B; ++i) {
+            if (i >= nrows) break;
             const int yr = (prow * B + i + sy) % ny;
             const size_t idx = vb + (size_t)yr * nz + zc;
             float2 v[K], xv[K], uv[K];
@@ -947,11 +1027,15 @@ __global__ void k_llr_finalize(ClassArgs a, int s0) {
 // launchers
 // ---------------------------------------------------------------------------
 
-bool fft_supported(int L) { return fft_length_supported(L); }
+bool fft_col_supported(int L) { return fft_col_length_supported(L); }
+bool fft_row_supported(int L) { return fft_row_length_supported(L); }
 
 int llr_workgroups(int ny, int nz, int b) {
-    if (b != 4 && b != 8 && b != 16) return 0;
-    const int strips = (ny / b) * ((nz + 63) / 64);   // one wave per strip of b rows x 64 columns
+    if (b != 4 && b != 8 && b != 12 && b != 16) return 0;
+    // one wave per strip of b rows x (64 / GW) blocks, GW = b rounded up to a power of two
+    const int bw = 64 / pow2_at_least(b);
+    const int nby = (ny + b - 1) / b, nbz = (nz + b - 1) / b;
+    const int strips = nby * ((nbz + bw - 1) / bw);
     return (strips + kThreads / 64 - 1) / (kThreads / 64);
 }
 
@@ -962,7 +1046,7 @@ bool reg_plan(int L, int* R1, int* R2) {
         *R1 = RegPlan<n>::R1;         \
         *R2 = RegPlan<n>::R2;         \
         return true;
-        X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+        X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(240) X(256) X(320) X(384) X(512)
 #undef X
     }
     return false;
@@ -973,12 +1057,15 @@ static size_t rows_lds() { return (L + kRowTile * RowGeom<L>::TB) * sizeof(float
 template <int L>
 static size_t cols_lds() { return (L + colB<L>() * RegGeom<L>::TB) * sizeof(float2); }
 
-#define T2S_FOR_LENGTHS(X) X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+// column lengths (every pass) and the row-only lengths (passes A and C)
+#define T2S_FOR_LENGTHS(X) \
+    X(16) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(240) X(256) X(320) X(384) X(512)
+#define T2S_FOR_ROW_LENGTHS(X) T2S_FOR_LENGTHS(X) X(260)
 
 size_t lds_bytes_passA(int nz) {
     switch (nz) {
 #define X(L) case L: return rows_lds<L>();
-        T2S_FOR_LENGTHS(X)
+        T2S_FOR_ROW_LENGTHS(X)
 #undef X
     }
     return 0;
@@ -1006,12 +1093,16 @@ hipError_t launch_passA(const ClassArgs& a, int s0, int count, const float2* src
                         PartialSrc gc, PartialSrc gp, int want_pp, hipStream_t st) {
     const dim3 grid(a.ny / kRowTile, a.K, count);
     switch (a.nz) {
-#define X(L)                                                                                                   \
-    case L:                                                                                                    \
-        hipLaunchKernelGGL(k_passA<L>, grid, dim3(rows_threads<L>()), 0, st, a, s0, src, src_s0, first, gc, gp, \
-                           want_pp);                                                                           \
+#define X(L)                                                                                                       \
+    case L:                                                                                                        \
+        if (a.M == 2)                                                                                              \
+            hipLaunchKernelGGL((k_passA<L, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, src, src_s0, first,   \
+                               gc, gp, want_pp);                                                                   \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_passA<L, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, src, src_s0, first,   \
+                               gc, gp, want_pp);                                                                   \
         break;
-        T2S_FOR_LENGTHS(X)
+        T2S_FOR_ROW_LENGTHS(X)
 #undef X
         default:
             return hipErrorInvalidValue;
@@ -1059,14 +1150,20 @@ hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float r
     switch (a.nz) {
 #define X(L)                                                                                                  \
     case L:                                                                                                   \
-        if (mode == 0)                                                                                        \
-            hipLaunchKernelGGL((k_passC<L, 0>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0, \
-                               none, 0);                                                                      \
+        if (mode == 0 && a.M == 2)                                                                            \
+            hipLaunchKernelGGL((k_passC<L, 0, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,    \
+                               out_s0, none, 0);                                                              \
+        else if (mode == 0)                                                                                   \
+            hipLaunchKernelGGL((k_passC<L, 0, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,    \
+                               out_s0, none, 0);                                                              \
+        else if (a.M == 2)                                                                                    \
+            hipLaunchKernelGGL((k_passC<L, 1, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,    \
+                               out_s0, none, 0);                                                              \
         else                                                                                                  \
-            hipLaunchKernelGGL((k_passC<L, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0, \
-                               none, 0);                                                                      \
+            hipLaunchKernelGGL((k_passC<L, 1, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,    \
+                               out_s0, none, 0);                                                              \
         break;
-        T2S_FOR_LENGTHS(X)
+        T2S_FOR_ROW_LENGTHS(X)
 #undef X
         default:
             return hipErrorInvalidValue;
@@ -1079,10 +1176,14 @@ hipError_t launch_passC_cg(const ClassArgs& a, int s0, int count, PartialSrc gc,
     switch (a.nz) {
 #define X(L)                                                                                                 \
     case L:                                                                                                  \
-        hipLaunchKernelGGL((k_passC<L, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, 0.0f, nullptr, 0, gc, \
-                           out_buf);                                                                         \
+        if (a.M == 2)                                                                                        \
+            hipLaunchKernelGGL((k_passC<L, 2, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, 0.0f, nullptr, 0, \
+                               gc, out_buf);                                                                 \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_passC<L, 2, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, 0.0f, nullptr, 0, \
+                               gc, out_buf);                                                                 \
         break;
-        T2S_FOR_LENGTHS(X)
+        T2S_FOR_ROW_LENGTHS(X)
 #undef X
         default:
             return hipErrorInvalidValue;
@@ -1138,6 +1239,7 @@ hipError_t launch_llr(const ClassArgs& a, int s0, int count, int mode, int k, co
     switch (a.block) {
         case 4: return launch_llr_b<4>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st);
         case 8: return launch_llr_b<8>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st);
+        case 12: return launch_llr_b<12>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st);
         case 16: return launch_llr_b<16>(a, s0, count, mode, k, in, out, tau, sy, sz, step, st);
         default: return hipErrorInvalidValue;
     }
@@ -1283,7 +1385,7 @@ __global__ __launch_bounds__(kThreads) void k_haar_denoise(ClassArgs a, int s0, 
     const int tile = blockIdx.x * kHaarTiles + w;
     const bool on = tile < ntiles;               // uniform over each wave
     const int by = q / 8, bz = q % 8;
-    float2* img = a.x + ((size_t)s * a.K + k) * a.ny * a.nz;
+    float2* img = a.x + ((size_t)s * a.M * a.K + k) * a.ny * a.nz;   // k: image index over M K
     const size_t g0 = on ? (size_t)((tile / ntz) * 16 + 2 * by) * a.nz + (tile % ntz) * 16 + 2 * bz : 0;
     float2 v00, v01, v10, v11;
     if (on) {
@@ -1329,22 +1431,22 @@ __global__ __launch_bounds__(kThreads) void k_haar_denoise(ClassArgs a, int s0, 
 
 hipError_t launch_haar_denoise(const ClassArgs& a, int s0, int count, int levels, float thr, hipStream_t st) {
     const int ntiles = (a.ny / 16) * (a.nz / 16);
-    const dim3 grid((ntiles + kHaarTiles - 1) / kHaarTiles, a.K, count);
+    const dim3 grid((ntiles + kHaarTiles - 1) / kHaarTiles, a.M * a.K, count);
     hipLaunchKernelGGL(k_haar_denoise, grid, dim3(kThreads), 0, st, a, s0, levels, thr);
     return hipGetLastError();
 }
 
-// out[s][j][n] = sum_k phi_te[j][k] alpha[s][k][n] for slices [s0, s0 + count)
-// (out holds slices from s0 on); one thread per voxel, all echo times at once
+// out[s][m][j][n] = sum_k phi_te[j][k] alpha[s][m][k][n] for slices [s0, s0 + count) and
+// map sets m (out holds slices from s0 on); one thread per voxel, all echo times at once
 struct PhiTe {
     float v[kMaxK * kMaxK];
 };
 __global__ __launch_bounds__(kThreads) void k_backproject(ClassArgs a, int s0, int nte, PhiTe ph, float2* out) {
-    const int s = s0 + blockIdx.y;
+    const int s = s0 + blockIdx.y, m = blockIdx.z;
     const size_t N = (size_t)a.ny * a.nz;
     const int K = a.K;
-    const float2* al = a.x + (size_t)s * K * N;
-    float2* o = out + (size_t)(s - s0) * nte * N;
+    const float2* al = a.x + ((size_t)s * a.M + m) * K * N;
+    float2* o = out + ((size_t)(s - s0) * a.M + m) * nte * N;
     for (size_t n = (size_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += (size_t)gridDim.x * kThreads) {
         float2 v[kMaxK];
 #pragma unroll
@@ -1369,7 +1471,7 @@ hipError_t launch_backproject(const ClassArgs& a, int s0, int count, int nte, co
         for (int k = 0; k < a.K; ++k) ph.v[j * kMaxK + k] = phi_te[j * a.K + k];
     const size_t N = (size_t)a.ny * a.nz;
     const int gx = (int)std::min<size_t>((N + kThreads - 1) / kThreads, 1024);
-    hipLaunchKernelGGL(k_backproject, dim3(gx, count), dim3(kThreads), 0, st, a, s0, nte, ph, out);
+    hipLaunchKernelGGL(k_backproject, dim3(gx, count, a.M), dim3(kThreads), 0, st, a, s0, nte, ph, out);
     return hipGetLastError();
 }
 
@@ -1383,14 +1485,14 @@ __global__ __launch_bounds__(kThreads) void k_normalize(ClassArgs a, int s0, flo
         fac = nn > 0.0 ? (float)(1.0 / sqrt(nn)) : 0.0f;
     }
     __syncthreads();
-    const size_t n = (size_t)a.K * a.ny * a.nz;
+    const size_t n = (size_t)a.M * a.K * a.ny * a.nz;
     float2* vs = v + (size_t)s * n;
     for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads)
         vs[i] = make_float2(vs[i].x * fac, vs[i].y * fac);
 }
 
 hipError_t launch_normalize(const ClassArgs& a, int s0, int count, float2* v, hipStream_t st) {
-    const size_t n = (size_t)a.K * a.ny * a.nz;
+    const size_t n = (size_t)a.M * a.K * a.ny * a.nz;
     const int gx = (int)std::min<size_t>((n + kThreads - 1) / kThreads, 1024);
     hipLaunchKernelGGL(k_normalize, dim3(gx, count), dim3(kThreads), 0, st, a, s0, v);
     return hipGetLastError();

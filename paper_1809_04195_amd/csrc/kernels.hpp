@@ -21,8 +21,11 @@ struct PartialSrc {
 // Device view of one shape class (all slices of the class in one allocation).
 struct ClassArgs {
     int ny, nz, C, K, T, P;      // grid, coils, subspace, echoes, samples per coil
+    int M;                       // coil-map sets (soft-SENSE): coefficient vectors hold M K
+                                 // images per slice, the maps C M
     int nrw, npb, nllr;          // partial-sum counts per slice: row-pass workgroups (passes A
                                  // and C: ny / kRowTile * K), pass-B workgroups, LLR workgroups
+                                 // (M runs, one per map set)
     int gbase;                   // global index of the class's slice 0
     int hist_len;                // outer-iteration capacity of the residual history
     int block;                   // LLR block edge
@@ -39,9 +42,9 @@ struct ClassArgs {
     const int* row_ptr;          // [ny nz + 1] over uncentred transposed positions q = z' ny + y'
     const int* ent_t;            // echo of each sample entry
     const int* ent_p;            // sample index (within a coil's P) of each entry
-    float2* sens;                // [S][C][ny][nz]
+    float2* sens;                // [S][C][M][ny][nz]
     float2* ksp;                 // [S][C][P]
-    float2 *b0, *x, *r, *p, *w, *z, *u;   // [S][K][ny][nz]
+    float2 *b0, *x, *r, *p, *w, *z, *u;   // [S][M][K][ny][nz]
     float2* tmp;                 // [S][C][K][nz/16][ny/16][16][16]  pass intermediate (k-space,
                                  // 16 x 16 tiles, y fastest inside a tile)
     double* pa;                  // [S][nrw]    ||p||^2 partials of pass A
@@ -108,7 +111,9 @@ hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, i
 // hist[s][counter] = sum of the LLR partials of slice s; counter += 1
 hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, hipStream_t st);
 
-bool fft_supported(int L);
+// lengths with an FFT plan: as a column length ny (all passes) / as a row length nz
+bool fft_col_supported(int L);
+bool fft_row_supported(int L);
 // workgroups of the LLR kernel per slice (one partial-sum slot each); 0 for an
 // unsupported block size
 int llr_workgroups(int ny, int nz, int b);

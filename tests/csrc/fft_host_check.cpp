@@ -1,5 +1,6 @@
-// CPU build of the library's FFT core (same source as the GPU kernels use), for
-// checking codelets, Stockham index arithmetic and radix plans against numpy.
+// CPU build of the library's FFT core (the same header the GPU kernels use): the
+// register codelets and the two-step plans L = R1 R2 of the passes, with the thread
+// mapping of the kernels emulated sequentially, for checks against numpy.
 #include <cmath>
 #include <vector>
 
@@ -7,69 +8,97 @@
 
 using namespace t2s;
 
-template <int L>
-static void run(int inv, int ntr, const float* in, float* out) {
-    const int ld = lds_ld(L);
-    std::vector<float2> a(ntr * ld), b(ntr * ld), tw(L);
-    for (int m = 0; m < L; ++m) {
-        const double ang = -2.0 * M_PI * m / L;
-        tw[m] = make_float2(float(std::cos(ang)), float(std::sin(ang)));
-    }
-    for (int t = 0; t < ntr; ++t)
-        for (int i = 0; i < L; ++i) a[t * ld + ph(i)] = make_float2(in[2 * (t * L + i)], in[2 * (t * L + i) + 1]);
-    float2* res = inv ? fft_emulate<L, true>(a.data(), b.data(), ntr, ld, tw.data())
-                      : fft_emulate<L, false>(a.data(), b.data(), ntr, ld, tw.data());
-    for (int t = 0; t < ntr; ++t)
-        for (int i = 0; i < L; ++i) {
-            out[2 * (t * L + i)] = res[t * ld + ph(i)].x;
-            out[2 * (t * L + i) + 1] = res[t * ld + ph(i)].y;
+static float2 root(int e, int L, bool inv) {   // W_L^(+-e), as the library's twiddle table
+    const double ang = -2.0 * M_PI * e / L;
+    return make_float2(float(std::cos(ang)), float((inv ? -1.0 : 1.0) * std::sin(ang)));
+}
+
+// Forward: step 1 per n2 < R2 (DFT_R1 of x[R2 n1 + n2], twiddle W_L^(n2 k1)), exchange,
+// step 3 per k1 < R1 (DFT_R2), X[k1 + R1 k2].  Inverse: the mirrored steps.
+template <int R1, int R2>
+static void two_step(int inv, const float* in, float* out) {
+    constexpr int L = R1 * R2;
+    std::vector<float2> slot(L);
+    if (!inv) {
+        for (int n2 = 0; n2 < R2; ++n2) {
+            float2 v[R1];
+            for (int n1 = 0; n1 < R1; ++n1) v[n1] = make_float2(in[2 * (R2 * n1 + n2)], in[2 * (R2 * n1 + n2) + 1]);
+            dft_dir<R1, false>(v);
+            for (int k1 = 0; k1 < R1; ++k1) slot[k1 * R2 + n2] = cmul(v[k1], root((n2 * k1) % L, L, false));
         }
+        for (int k1 = 0; k1 < R1; ++k1) {
+            float2 b[R2];
+            for (int n2 = 0; n2 < R2; ++n2) b[n2] = slot[k1 * R2 + n2];
+            dft_dir<R2, false>(b);
+            for (int k2 = 0; k2 < R2; ++k2) {
+                out[2 * (k1 + R1 * k2)] = b[k2].x;
+                out[2 * (k1 + R1 * k2) + 1] = b[k2].y;
+            }
+        }
+    } else {
+        for (int k1 = 0; k1 < R1; ++k1) {
+            float2 b[R2];
+            for (int k2 = 0; k2 < R2; ++k2) b[k2] = make_float2(in[2 * (k1 + R1 * k2)], in[2 * (k1 + R1 * k2) + 1]);
+            dft_dir<R2, true>(b);
+            for (int m1 = 0; m1 < R2; ++m1) slot[m1 * R1 + k1] = cmul(b[m1], root((k1 * m1) % L, L, true));
+        }
+        for (int m1 = 0; m1 < R2; ++m1) {
+            float2 v[R1];
+            for (int k1 = 0; k1 < R1; ++k1) v[k1] = slot[m1 * R1 + k1];
+            dft_dir<R1, true>(v);
+            for (int m2 = 0; m2 < R1; ++m2) {
+                out[2 * (m1 + R2 * m2)] = v[m2].x;
+                out[2 * (m1 + R2 * m2) + 1] = v[m2].y;
+            }
+        }
+    }
+}
+
+// which = 0: the column plan RegPlan<L>; 1: the row plan RowPlan<L>
+extern "C" int plan_host(int L, int which, int inv, const float* in, float* out) {
+#define COL(n) \
+    case n: two_step<RegPlan<n>::R1, RegPlan<n>::R2>(inv, in, out); return 0;
+#define ROW(n) \
+    case n: two_step<RowPlan<n>::R1, RowPlan<n>::R2>(inv, in, out); return 0;
+    if (which == 0) {
+        switch (L) { COL(16) COL(32) COL(48) COL(64) COL(96) COL(128) COL(160) COL(192) COL(240) COL(256) COL(320) COL(384) COL(512) }
+    } else {
+        switch (L) { ROW(16) ROW(32) ROW(48) ROW(64) ROW(96) ROW(128) ROW(160) ROW(192) ROW(240) ROW(256) ROW(260) ROW(320) ROW(384) ROW(512) }
+    }
+#undef COL
+#undef ROW
+    return -1;
+}
+
+extern "C" int plan_factors(int L, int which, int* R1, int* R2) {
+#define F(P, n) \
+    case n: *R1 = P<n>::R1; *R2 = P<n>::R2; return 0;
+    if (which == 0) {
+        switch (L) { F(RegPlan, 16) F(RegPlan, 32) F(RegPlan, 48) F(RegPlan, 64) F(RegPlan, 96) F(RegPlan, 128) F(RegPlan, 160) F(RegPlan, 192) F(RegPlan, 240) F(RegPlan, 256) F(RegPlan, 320) F(RegPlan, 384) F(RegPlan, 512) }
+    } else {
+        switch (L) { F(RowPlan, 16) F(RowPlan, 32) F(RowPlan, 48) F(RowPlan, 64) F(RowPlan, 96) F(RowPlan, 128) F(RowPlan, 160) F(RowPlan, 192) F(RowPlan, 240) F(RowPlan, 256) F(RowPlan, 260) F(RowPlan, 320) F(RowPlan, 384) F(RowPlan, 512) }
+    }
+#undef F
+    return -1;
 }
 
 template <int R>
-static void run_codelet(const float* in, float* out) {
+static void run_codelet(int inv, const float* in, float* out) {
     float2 v[R];
     for (int r = 0; r < R; ++r) v[r] = make_float2(in[2 * r], in[2 * r + 1]);
-    dft<R>(v);
+    if (inv) dft_dir<R, true>(v);
+    else dft_dir<R, false>(v);
     for (int r = 0; r < R; ++r) {
         out[2 * r] = v[r].x;
         out[2 * r + 1] = v[r].y;
     }
 }
 
-extern "C" int fft_host(int L, int inv, int ntr, const float* in, float* out) {
-    switch (L) {
-        case 16: run<16>(inv, ntr, in, out); return 0;
-        case 32: run<32>(inv, ntr, in, out); return 0;
-        case 48: run<48>(inv, ntr, in, out); return 0;
-        case 64: run<64>(inv, ntr, in, out); return 0;
-        case 96: run<96>(inv, ntr, in, out); return 0;
-        case 128: run<128>(inv, ntr, in, out); return 0;
-        case 160: run<160>(inv, ntr, in, out); return 0;
-        case 192: run<192>(inv, ntr, in, out); return 0;
-        case 256: run<256>(inv, ntr, in, out); return 0;
-        case 320: run<320>(inv, ntr, in, out); return 0;
-        case 384: run<384>(inv, ntr, in, out); return 0;
-        case 512: run<512>(inv, ntr, in, out); return 0;
-    }
-    return -1;
-}
-
-extern "C" int codelet_host(int R, const float* in, float* out) {
-    switch (R) {
-        case 2: run_codelet<2>(in, out); return 0;
-        case 3: run_codelet<3>(in, out); return 0;
-        case 4: run_codelet<4>(in, out); return 0;
-        case 5: run_codelet<5>(in, out); return 0;
-        case 6: run_codelet<6>(in, out); return 0;
-        case 8: run_codelet<8>(in, out); return 0;
-        case 10: run_codelet<10>(in, out); return 0;
-        case 12: run_codelet<12>(in, out); return 0;
-        case 16: run_codelet<16>(in, out); return 0;
-        case 20: run_codelet<20>(in, out); return 0;
-        case 24: run_codelet<24>(in, out); return 0;
-        case 32: run_codelet<32>(in, out); return 0;
-    }
+extern "C" int codelet_host(int R, int inv, const float* in, float* out) {
+#define C(n) \
+    case n: run_codelet<n>(inv, in, out); return 0;
+    switch (R) { C(2) C(3) C(4) C(5) C(6) C(8) C(10) C(12) C(13) C(15) C(16) C(20) C(24) C(32) }
+#undef C
     return -1;
 }
 

@@ -39,7 +39,7 @@ def dft_matrix(n):
     return np.exp(-2j * np.pi * j * i / n) / np.sqrt(n)
 
 
-@pytest.mark.parametrize("ny,nz", [(4, 4), (6, 10), (12, 8), (12, 20), (24, 40), (10, 6)])
+@pytest.mark.parametrize("ny,nz", [(4, 4), (6, 10), (12, 8), (12, 20), (24, 40), (10, 6), (26, 30)])
 def test_fft2c_matches_direct_dft(ny, nz):
     rng = np.random.default_rng(ny * 100 + nz)
     x = crandn(rng, 2, ny, nz)
@@ -53,6 +53,18 @@ def test_fft2c_matches_direct_dft(ny, nz):
     assert rel(O.fft2c(x)[1], Dy @ x[1] @ Dz.T) < 1e-12
     assert rel(O.ifft2c(O.fft2c(x)), x) < 1e-12
     assert rel(O.ifft2c(x)[1], Dy.conj().T @ x[1] @ Dz.conj()) < 1e-12
+
+
+def test_fft2c_paper_grid_matches_direct_dft():
+    # the paper's 260 x 240 slice grid (260 = 4 5 13, 240 = 16 15), matrix form
+    ny, nz = 240, 260
+    rng = np.random.default_rng(260)
+    x = crandn(rng, ny, nz)
+    Dy, Dz = dft_matrix(ny), dft_matrix(nz)
+    assert rel(O.fft2c(x), Dy @ x @ Dz.T) < 1e-12
+    jy, jz = 7, 201
+    brute = np.sum(Dy[jy][:, None] * Dz[jz][None, :] * x)
+    assert abs(O.fft2c(x)[jy, jz] - brute) < 1e-12 * abs(brute)
 
 
 @pytest.mark.parametrize("nx", [4, 6, 16, 20])
@@ -485,3 +497,91 @@ def test_admm_tolerance_degenerate_slices():
     assert res.n_outer < 300 and res.history[-1]["res"] <= 1e-4
     assert np.linalg.norm(res.z) == 0.0
     assert np.linalg.norm(res.alpha) <= 1e-4 * 0.01 * np.linalg.norm(O.adjoint(y, sens, phi, masks)) * 1.0001
+
+
+# --- partial LLR blocks (a block edge that does not divide the grid) --------------------
+
+
+@pytest.mark.parametrize("n,b,sh", [(20, 8, 3), (260, 12, 11), (240, 12, 0), (16, 16, 5), (9, 4, 2)])
+def test_block_ranges_partition_the_axis(n, b, sh):
+    ranges = O.block_ranges(n, b, sh)
+    allidx = np.concatenate(ranges)
+    assert sorted(allidx.tolist()) == list(range(n))          # every index in exactly one block
+    sizes = [r.size for r in ranges]
+    assert sizes[:-1] == [b] * (len(ranges) - 1) and sizes[-1] == n - (len(ranges) - 1) * b
+    assert ranges[0][0] == sh % n                              # block 0 starts at the shift
+
+
+def test_llr_partial_blocks_single_pass_equals_explicit():
+    # modular gather of the single pass vs circular shift + contiguous tiles cut short
+    rng = np.random.default_rng(21)
+    v = crandn(rng, 3, 20, 28)
+    for shift in ((0, 0), (3, 5), (7, 7)):
+        assert rel(O.llr_prox(v, 0.8, shift, 8), O.llr_prox_explicit(v, 0.8, shift, 8)) < 1e-12
+    v = crandn(rng, 4, 24, 26)
+    assert rel(O.llr_prox(v, 0.5, (11, 4), 12), O.llr_prox_explicit(v, 0.5, (11, 4), 12)) < 1e-12
+
+
+def test_llr_partial_block_rank_one_shrunk_by_tau():
+    # a rank-1 pattern sigma u v^H filling exactly the partial corner block (wrapped by
+    # the shift) and zero elsewhere comes back as (sigma - tau) u v^H; other blocks stay 0
+    K, Ny, Nz, b, shift = 3, 20, 26, 8, (6, 5)
+    rows = O.block_ranges(Ny, b, shift[0])[-1]
+    cols = O.block_ranges(Nz, b, shift[1])[-1]
+    assert rows.size == 4 and cols.size == 2
+    rng = np.random.default_rng(22)
+    uvec = crandn(rng, rows.size * cols.size)
+    uvec /= np.linalg.norm(uvec)
+    vvec = crandn(rng, K)
+    vvec /= np.linalg.norm(vvec)
+    sigma, tau = 3.0, 0.7
+    X = sigma * np.outer(uvec, vvec.conj())                  # [voxels, K]
+    v = np.zeros((K, Ny, Nz), dtype=complex)
+    v[:, rows[:, None], cols[None, :]] = X.T.reshape(K, rows.size, cols.size)
+    out = O.llr_prox(v, tau, shift, b)
+    assert rel(out, v * (sigma - tau) / sigma) < 1e-12
+
+
+# --- soft-SENSE: M = 2 coil-map sets (Sec. II-A) -------------------------------------------
+
+
+def test_two_map_sets_adjoint_identity_and_routes():
+    rng = np.random.default_rng(31)
+    phi, s1, masks = small_problem(rng, ny=12, nz=14, C=3, T=6, K=3)
+    sens = np.stack([s1, 0.5 * crandn(rng, *s1.shape)], axis=1)          # [C, 2, Ny, Nz]
+    alpha = crandn(rng, 2, 3, 12, 14)
+    y = crandn(rng, 3, int(masks.sum()))
+    lhs = np.vdot(y, O.forward(alpha, sens, phi, masks))
+    rhs = np.vdot(O.adjoint(y, sens, phi, masks), alpha)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    psi = O.space_time_kernel(phi, masks)
+    assert rel(O.normal_psi(alpha, sens, psi), O.normal_explicit(alpha, sens, phi, masks)) < 1e-12
+
+
+def test_two_map_sets_reduce_to_one():
+    # a second map set of zeros leaves the first set's problem unchanged and gets nothing
+    # back; coil images are the sum over map sets (swapping the sets swaps the results)
+    rng = np.random.default_rng(32)
+    phi, s1, masks = small_problem(rng, ny=12, nz=10, C=2, T=5, K=2)
+    alpha = crandn(rng, 2, 2, 12, 10)
+    psi = O.space_time_kernel(phi, masks)
+    sens = np.stack([s1, np.zeros_like(s1)], axis=1)
+    out = O.normal_psi(alpha, sens, psi)
+    assert rel(out[0], O.normal_psi(alpha[0], s1, psi)) < 1e-12
+    assert np.abs(out[1]).max() == 0
+    y = O.forward(alpha, sens, phi, masks)
+    assert rel(y, O.forward(alpha[0], s1, phi, masks)) < 1e-12
+    s2 = crandn(rng, *s1.shape)
+    both = np.stack([s1, s2], axis=1)
+    swapped = np.stack([s2, s1], axis=1)
+    assert rel(O.forward(alpha, both, phi, masks), O.forward(alpha[::-1], swapped, phi, masks)) < 1e-12
+    a = O.adjoint(y, both, phi, masks)
+    assert rel(a[0], O.adjoint(y, s1, phi, masks)) < 1e-12 and rel(a[1], O.adjoint(y, s2, phi, masks)) < 1e-12
+
+
+def test_two_map_sets_llr_per_set():
+    rng = np.random.default_rng(33)
+    v = crandn(rng, 2, 3, 16, 24)
+    out = O.llr_prox(v, 0.6, (3, 5), 8)
+    assert rel(out[0], O.llr_prox(v[0], 0.6, (3, 5), 8)) < 1e-14
+    assert rel(out[1], O.llr_prox(v[1], 0.6, (3, 5), 8)) < 1e-14
