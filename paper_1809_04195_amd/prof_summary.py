@@ -32,8 +32,7 @@ CU_NUM, SIMD_NUM, XCD_NUM = 256, 1024, 8
 COPY_PROBE_BYTES = 1 << 30
 
 FAMILIES = (
-    ("k_passA", "pass_a"), ("k_passB_inv", "passB_inv"), ("k_passB", "pass_b"), ("k_passC<256, 1>", "passC_adjoint"),
-    ("k_passC", "pass_c"), ("k_llr_finalize", "llr_finalize"), ("k_llr", "llr_admm"), ("k_project", "load_project"),
+    ("k_passA", "pass_a"), ("k_passB_inv", "passB_inv"), ("k_passB", "pass_b"), ("k_llr_finalize", "llr_finalize"), ("k_llr", "llr_admm"), ("k_project", "load_project"),
     ("k_init", "init"), ("k_set_state", "set_state"), ("copyBuffer", "copy"),
     ("k_conv", "unet_conv"), ("k_wgrad_reduce", "unet_wgrad_reduce"), ("k_wgrad", "unet_wgrad"),
     ("k_adam", "unet_adam"), ("k_pool_bwd", "unet_pool_bwd"), ("k_pool", "unet_pool"), ("k_unshuffle", "unet_unshuffle"),
@@ -43,6 +42,13 @@ FAMILIES = (
 
 
 def family(name):
+    # k_passC<L, MODE, M>: MODE 1 is the adjoint of the load step, 0 the normal operator
+    # of apply_normal / set_initial, 2 the CG step
+    if "k_passC<" in name:
+        args = name.split("k_passC<", 1)[1].split(">", 1)[0].split(",")
+        if len(args) > 1 and args[1].strip() == "1":
+            return "passC_adjoint"
+        return "pass_c"
     for key, fam in FAMILIES:
         if key in name:
             return fam

@@ -193,8 +193,8 @@ def run_tolerance(phi, cl, cfg, start, net=None, batch=16, mode=T2S_BATCHED_GRAP
 # Workloads: the training geometry (2D phantoms, its own masks) follows the volume
 # the network is evaluated on; targets are the fixed 100 x 5 schedule's solution.
 WORKLOADS = {
-    "eval320": dict(eval_cfg=3, ny=256, nz=256, C=8, frac=0.015, chunk=800),
-    "vol512": dict(eval_cfg=4, ny=384, nz=384, C=16, frac=0.01, chunk=200),
+    "eval320": dict(eval_cfg=3, ny=256, nz=256, C=8, K=4, frac=0.015, chunk=800),
+    "vol512": dict(eval_cfg=4, ny=384, nz=384, C=16, K=5, frac=0.01, chunk=200),
 }
 
 
@@ -222,7 +222,9 @@ def main():
     args = ap.parse_args()
     wl = WORKLOADS[args.workload]
     args.out = args.out or f"warmstart_out/warmstart_{args.workload}.json"
-    args.save_params = args.save_params or f"warmstart_out/unet_params_{args.workload}.npy"
+    if not args.save_params:   # the parameters bench.py and the warm-start runs load
+        args.save_params = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                                        f"unet_{args.workload}_{wl['ny']}x{wl['nz']}_k{wl['K']}.npy")
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
 
     import torch
