@@ -132,10 +132,10 @@ __device__ __forceinline__ void st_stream(float2* p, float2 v) {
         *p = v;
     }
 }
-// Pass B at 384 points per column (K = 5, 16 coils) measured 2.5 % slower with
-// nontemporal accesses, at 256 points 6 % faster; passes A and C gain at both sizes.
+// Pass B streams its intermediate nontemporally at every length (at 384 points this
+// gained 10 % once the Psi table is shared through each XCD's L2, at 256 points 6 %).
 template <int L>
-constexpr bool passB_nt() { return L < 384; }
+constexpr bool passB_nt() { return true; }
 
 __device__ __forceinline__ bool slice_active(const ClassArgs& a, int s) { return a.state[4 * s] != 0; }
 

@@ -283,14 +283,30 @@ __global__ void k_wgrad_reduce(const float* part, int nsplit, int taps, int cout
     grad[i] = (float)s;
 }
 
-// bias gradient partials: part[split][c] = sum_{p in split} dout[p][co_off + c], c < C
+// bias gradient partials: part[split][c] = sum_{p in split} dout[p][co_off + c], c < C.
+// The 256 threads cover rows = 256 / C pixels at a time (channel fastest, so a wave
+// reads whole pixel rows of channels), each summing every rows-th pixel of the split;
+// the rows are then added in LDS in a fixed order.
 __global__ void k_bias_part(const bf16* dout, int ldo, int co_off, int C, int P, int pix_per_split, float* part) {
+    __shared__ float red[256];
     const int split = blockIdx.x;
     const int p0 = split * pix_per_split, p1 = min(P, p0 + pix_per_split);
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    const int tid = threadIdx.x;
+    for (int cb = 0; cb < C; cb += 256) {
+        const int cw = min(256, C - cb);          // channels of this pass
+        const int rows = 256 / cw;
+        const int c = cb + tid % cw, row = tid / cw;
         float s = 0.f;
-        for (int p = p0; p < p1; ++p) s += bf2f(dout[(size_t)p * ldo + co_off + c]);
-        part[(size_t)split * C + c] = s;
+        if (row < rows)
+            for (int p = p0 + row; p < p1; p += rows) s += bf2f(dout[(size_t)p * ldo + co_off + c]);
+        __syncthreads();
+        red[tid] = s;
+        __syncthreads();
+        if (tid < cw) {
+            float t = 0.f;
+            for (int r = 0; r < rows; ++r) t += red[r * cw + tid];
+            part[(size_t)split * C + cb + tid] = t;
+        }
     }
 }
 
@@ -653,7 +669,7 @@ int wgrad(t2s_unet* u, const Layer& Ly, const bf16* dout, int ldo, int co_off, c
     ULAUNCH();
     // bias: sum of dout over pixels (folding the 4 sub-pixel groups of an up layer)
     const int C = Ly.cout;
-    const int bsplit = std::max(1, std::min(256, P / 512));
+    const int bsplit = std::max(1, std::min(1024, P / 256));
     const int bpps = (P + bsplit - 1) / bsplit;
     if ((size_t)bsplit * C > u->bpart_floats) return ufail(T2S_ENOMEM, "bias partial buffer");
     hipLaunchKernelGGL(unetk::k_bias_part, dim3(bsplit), dim3(256), 0, st, dout, ldo, co_off, C, P, bpps,

@@ -65,6 +65,8 @@ def _create(phi, cls, **kw):
     ("bad_mask", T.T2S_EINVAL),
     ("zero_coils", T.T2S_ESHAPE),
     ("tol_without_window", T.T2S_EINVAL),
+    ("bad_nmaps", T.T2S_ESHAPE),
+    ("ny_not_a_column_length", T.T2S_ESHAPE),
 ])
 def test_plan_create_rejects(case, expected):
     phi = _phi()
@@ -95,6 +97,10 @@ def test_plan_create_rejects(case, expected):
         cls = [(32, 48, 0, 1, masks)]
     elif case == "tol_without_window":
         kw.update(tol=1e-4, freeze_window=0)
+    elif case == "bad_nmaps":
+        cls = [(32, 48, 2, 1, masks, 3)]
+    elif case == "ny_not_a_column_length":
+        cls = [(260, 48, 2, 1, np.ones((6, 260, 48), np.uint8))]
     code, h = _create(phi, cls, **kw)
     assert code == expected, (code, T.t2s_last_error())
     assert T.t2s_last_error()
@@ -224,16 +230,32 @@ def test_block_shift_matches_oracle():
                     assert T.t2s_block_shift(seed, g, k, b) == O.block_shift(seed, g, k, b)
 
 
-def test_host_inputs_nonfinite_rejected_before_gpu():
-    # load_slices checks host data before touching the device; use an unbound plan
-    # whose state check comes later than the finiteness check? No: state is first.
-    # So bind is required; this is covered by the GPU tests.  Here: set_initial on an
-    # unloaded slice is a state error.
+def test_set_initial_before_load_is_a_state_error():
     phi = _phi()
     cls, masks = _classes()
     code, h = _create(phi, cls)
     a0 = np.zeros((1, 3, 32, 48), np.complex64)
     assert T.lib().t2s_set_initial(h, 0, 0, 1, a0.ctypes.data, 0, None) == T.T2S_ESTATE
+    T.t2s_plan_destroy(h)
+
+
+def test_nonfinite_host_inputs_rejected_without_touching_the_gpu():
+    # NaN / Inf in host inputs that are checked before any HIP call: the basis at plan
+    # creation and the echo-time rows of the back-projection (slices with data need a
+    # bound workspace, so their checks run in the GPU tests)
+    cls, masks = _classes()
+    for bad in (np.nan, np.inf):
+        phi = _phi()
+        phi[1, 0] = bad
+        code, h = _create(phi, cls)
+        assert code == T.T2S_ENONFINITE
+    code, h = _create(_phi(), cls)
+    assert code == 0
+    ph = np.ones((2, 3), np.float32)
+    ph[0, 2] = np.nan
+    out = np.zeros(1, np.complex64)
+    assert T.lib().t2s_backproject(h, 0, 0, 1, 2, ph.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.ctypes.data,
+                                   None) == T.T2S_ENONFINITE
     T.t2s_plan_destroy(h)
 
 
@@ -271,3 +293,24 @@ def test_unet_init_params_follow_packing():
     L.t2s_unet_init_params(h, ctypes.c_uint64(7), q.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
     assert np.array_equal(p, q)
     L.t2s_unet_destroy(h)
+
+
+def test_paper_grid_two_map_sets_and_twelve_point_blocks_accepted():
+    # 240 x 260 (260 a row length only), two coil-map sets, 12 x 12 blocks (partial at
+    # the end of the 260-point axis); the workspace grows with the map sets and holds
+    # the intermediate in whole 16-column tiles (272 columns)
+    q, _ = np.linalg.qr(np.random.default_rng(2).standard_normal((8, 4)))
+    phi = q.astype(np.float32)
+    masks = (np.random.default_rng(3).random((8, 240, 260)) < 0.05).astype(np.uint8)
+    sizes = {}
+    for nm in (1, 2):
+        code, h = _create(phi, [(240, 260, 7, 1, masks, nm)], block=12)
+        assert code == 0, T.t2s_last_error()
+        sizes[nm] = T.t2s_plan_workspace_bytes(h)
+        T.t2s_plan_destroy(h)
+    # one slice: maps C N and seven coefficient vectors K N per map set, 8 bytes each
+    assert sizes[2] - sizes[1] >= 8 * 240 * 260 * (7 + 7 * 4)
+    code, h = _create(phi, [(240, 260, 7, 1, masks)], block=12)
+    tiles = T.t2s_plan_workspace_bytes(h)
+    T.t2s_plan_destroy(h)
+    assert tiles >= 7 * 4 * 240 * 272 * 8
