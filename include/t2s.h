@@ -208,7 +208,8 @@ int t2s_set_order(t2s_plan* plan, int cls, int order);
 /* Global index of class `cls`'s slice 0 in the block-shift schedule (default: the
  * number of slices in the classes before it).  Lets a volume be split over several
  * plans (or devices) with every slice keeping the shifts, and so the result, it has
- * in one plan.  Errors: T2S_EINVAL. */
+ * in one plan.  Host-side: it reaches the device with the next t2s_load_slices,
+ * t2s_set_initial, t2s_reconstruct or t2s_fista.  Errors: T2S_EINVAL. */
 int t2s_set_slice_offset(t2s_plan* plan, int cls, int first_global);
 int t2s_get_order(const t2s_plan* plan, int cls, int* order);
 
@@ -394,6 +395,61 @@ int t2s_unet_get_adam_state(t2s_unet* net, float* m, float* v, int* step, void* 
  * (standard deviation sqrt(2 / fan_in)) from a 64-bit Mersenne twister seeded with
  * `seed`, zero biases, the final 1x1 layer scaled by 0.1. */
 int t2s_unet_init_params(const t2s_unet* net, uint64_t seed, float* params);
+
+/* Shape of a network: K (complex channels), max_batch, H, W.  Any pointer may be NULL. */
+int t2s_unet_get_shape(const t2s_unet* net, int* K, int* max_batch, int* H, int* W);
+
+/* ---- Streaming a volume through a plan's slices (continuous batching) ----
+ *
+ * The per-slice problems of eq. t2shpics are independent (Sec. II-A: after the
+ * readout transform every slice is reconstructed on its own; Sec. IV-E spreads them
+ * over machines), and in tolerance mode they stop after different numbers of outer
+ * iterations.  Instead of solving fixed batches, whose launches thin out as slices
+ * stop, a one-class plan's S slices become slots fed from a queue of slices: at every
+ * stop decision (each check_every outer iterations of a slot) the slots whose slice
+ * stopped are refilled with the next queued slices (load: projection and adjoint;
+ * optional network warm start; then the slot joins the next outer iteration).  Every
+ * slice runs exactly the arithmetic, stop and freeze decisions it has in
+ * t2s_reconstruct (its own outer counter from 0, its own global index in the shift
+ * schedule), so results equal those of a batch solve of the same slices.
+ *
+ * t2s_stream_open: start streaming on plan class `cls` (the plan must have exactly
+ * one class, a bound workspace and tol > 0 or a fixed n_outer), all slots idle, queue
+ * empty.  `net` (may be NULL: cold start) gives each loaded slice alpha0 = net(b0) as
+ * t2s_set_initial does; it must have K, H = ny, W = nz of the class and M = 1.  `mode`
+ * is T2S_BATCHED or T2S_BATCHED_GRAPH (an outer iteration replayed from a captured
+ * graph; profiling forces eager launches).  Errors: T2S_EINVAL, T2S_ESHAPE (net shape),
+ * T2S_ESTATE (workspace not bound).
+ *
+ * t2s_stream_submit: append `count` slices to the queue (no GPU work): their coil maps
+ * `sens` (device complex64 [count][C][M][ny][nz]) and samples `ksp` (device complex64
+ * [count][C][P], P the class's samples per coil), global indices first_global .. +
+ * count - 1 in the shift schedule, and where to put the results: `alpha_out` (device
+ * complex64 [count][M][K][ny][nz]) and `reports` (host, count entries, or NULL).  The
+ * arrays must stay valid until the slices completed; the same arrays may be submitted
+ * again.  Errors: T2S_EINVAL, T2S_ESTATE (not open).
+ *
+ * t2s_stream_run: refill, iterate and decide until at least `min_done` more slices
+ * completed in this call (min_done <= 0: until the queue is empty and every slot idle)
+ * or nothing is left; `status` (may be NULL) receives the counts since open.  The
+ * results of completed slices are written on `stream` (synchronise it before reading
+ * them).  A slice that reaches n_outer before tol completes with converged = 0 and the
+ * call returns T2S_WNOTCONVERGED after finishing its work.  Errors: T2S_ESTATE (not
+ * open), T2S_EHIP.
+ *
+ * t2s_stream_close: end streaming (queued slices are dropped); the plan can then be
+ * used with t2s_load_slices / t2s_reconstruct again. */
+typedef struct t2s_stream_status {
+    int done;              /* slices completed since open                            */
+    int in_flight;         /* slices loaded or queued and not completed              */
+    int64_t loaded;        /* slices loaded into slots since open                    */
+    int64_t slice_outer;   /* outer iterations run, summed over slices, since open   */
+} t2s_stream_status;
+int t2s_stream_open(t2s_plan* plan, int cls, t2s_unet* net, int mode);
+int t2s_stream_submit(t2s_plan* plan, int count, int first_global, const void* sens, const void* ksp,
+                      void* alpha_out, t2s_slice_report* reports);
+int t2s_stream_run(t2s_plan* plan, int min_done, t2s_stream_status* status, void* stream);
+int t2s_stream_close(t2s_plan* plan);
 
 /* One 16x16x16 bf16 matrix-core product D = A B (host fp32 row-major, rounded to bf16
  * on input) -- a check of the lane layout the convolution kernels assume. */

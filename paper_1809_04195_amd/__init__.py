@@ -87,6 +87,15 @@ class t2s_slice_report(ctypes.Structure):
     ]
 
 
+class t2s_stream_status(ctypes.Structure):
+    _fields_ = [
+        ("done", ctypes.c_int),
+        ("in_flight", ctypes.c_int),
+        ("loaded", ctypes.c_int64),
+        ("slice_outer", ctypes.c_int64),
+    ]
+
+
 class T2SError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"t2s error {code}: {msg}")
@@ -146,6 +155,13 @@ _SIGS = {
     "t2s_unet_get_params": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p], ctypes.c_int),
     "t2s_unet_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
                          ctypes.c_int),
+    "t2s_unet_get_shape": ([ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 4, ctypes.c_int),
+    "t2s_stream_open": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "t2s_stream_submit": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p, ctypes.POINTER(t2s_slice_report)], ctypes.c_int),
+    "t2s_stream_run": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(t2s_stream_status), ctypes.c_void_p],
+                       ctypes.c_int),
+    "t2s_stream_close": ([ctypes.c_void_p], ctypes.c_int),
     "t2s_unet_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
                              ctypes.POINTER(ctypes.c_double), ctypes.c_void_p], ctypes.c_int),
     "t2s_unet_loss_grad": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
@@ -299,8 +315,35 @@ def t2s_read_coeffs(plan, cls, first, count, out, which=T2S_ALPHA, stream=None):
 def t2s_get_slice_report(plan, cls, slice_):
     r = t2s_slice_report()
     _check(lib().t2s_get_slice_report(plan, cls, slice_, ctypes.byref(r)))
+    return _report_dict(r)
+
+
+def _report_dict(r):
     return dict(outer_iterations=r.outer_iterations, k_freeze=r.k_freeze, converged=r.converged,
                 r_primal=r.r_primal, r_dual=r.r_dual)
+
+
+def t2s_stream_open(plan, cls=0, net=None, mode=T2S_BATCHED_GRAPH):
+    """net: a UNet (or its handle) for the warm start, None for a cold start."""
+    h = None if net is None else getattr(net, "handle", net)
+    return _check(lib().t2s_stream_open(plan, cls, h, mode))
+
+
+def t2s_stream_submit(plan, count, first_global, sens, ksp, alpha_out, reports=None):
+    """reports: a ctypes array of `count` t2s_slice_report (kept alive by the caller) or None."""
+    return _check(lib().t2s_stream_submit(plan, count, first_global, _ptr(sens), _ptr(ksp), _ptr(alpha_out),
+                                          reports))
+
+
+def t2s_stream_run(plan, min_done=0, stream=None):
+    """(code, {done, in_flight, loaded, slice_outer}: counts since open)."""
+    st = t2s_stream_status()
+    code = _check(lib().t2s_stream_run(plan, min_done, ctypes.byref(st), _stream(stream)), allow_warn=True)
+    return code, dict(done=st.done, in_flight=st.in_flight, loaded=st.loaded, slice_outer=st.slice_outer)
+
+
+def t2s_stream_close(plan):
+    return _check(lib().t2s_stream_close(plan))
 
 
 def t2s_apply_normal(plan, cls, first, count, inp, out, rho_add=0.0, stream=None):
@@ -456,6 +499,33 @@ class Plan:
 
     def report(self, cls, s):
         return t2s_get_slice_report(self.handle, cls, s)
+
+    # continuous batching: the slices of a one-class plan become slots fed from a queue
+    def stream_open(self, net=None, mode=T2S_BATCHED_GRAPH):
+        self._stream_reports = []
+        return t2s_stream_open(self.handle, 0, net, mode)
+
+    def stream_submit(self, sens, ksp, alpha_out, first_global):
+        """Queue the slices of device tensors sens [n][C](M)[ny][nz] and ksp [n][C][P];
+        results go to alpha_out [n](M)[K][ny][nz]; returns the report array (filled as
+        slices complete; `stream_reports` turns it into dicts)."""
+        n = sens.shape[0]
+        if ksp.shape[0] != n or alpha_out.shape[0] != n:
+            raise ValueError("sens, ksp and alpha_out must hold the same number of slices")
+        rep = (t2s_slice_report * n)()
+        self._stream_reports.append(rep)     # the library writes into it until the slices complete
+        t2s_stream_submit(self.handle, n, first_global, sens, ksp, alpha_out, rep)
+        return rep
+
+    def stream_run(self, min_done=0, stream=None):
+        return t2s_stream_run(self.handle, min_done, stream)
+
+    def stream_close(self):
+        return t2s_stream_close(self.handle)
+
+    @staticmethod
+    def stream_reports(rep):
+        return [_report_dict(r) for r in rep]
 
     def close(self):
         if self.handle is not None:

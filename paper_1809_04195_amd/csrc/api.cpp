@@ -68,6 +68,34 @@ struct Sched {
 std::mutex g_sched_mu;
 std::map<SchedKey, Sched> g_sched;
 
+// Continuous batching: a queue of submitted slice ranges and the slot each slice of
+// the one-class plan holds.
+struct StreamItem {
+    int count = 0, g0 = 0, next = 0;        // slices, global index of the first, next one to load
+    const char* sens = nullptr;
+    const char* ksp = nullptr;
+    char* out = nullptr;
+    t2s_slice_report* rep = nullptr;
+};
+struct StreamSlot {
+    int item = -1;                          // queue entry of the slice held (-1: idle)
+    int j = 0;                              // slice within the entry
+    int k = 0;                              // outer iterations run since the load
+};
+struct StreamState {
+    bool open = false, fresh = false;
+    int cls = 0, mode = 0;
+    t2s_unet* net = nullptr;
+    int net_batch = 0;
+    std::vector<StreamItem> items;
+    size_t head = 0;                        // first entry with slices left to load
+    std::vector<StreamSlot> slots;
+    long done = 0;
+    int64_t loaded = 0, slice_outer = 0;
+    double* hpin = nullptr;                 // pinned host copies of the history and ||b0||^2 partials
+    size_t hpin_len = 0;
+};
+
 }  // namespace
 
 namespace t2s {
@@ -101,6 +129,7 @@ struct t2s_plan {
     int hist_len = 0;
     bool reconstructed = false;
     hipStream_t last_stream = nullptr;
+    StreamState stream;
 };
 
 namespace {
@@ -141,7 +170,6 @@ void fill_args(t2s_plan* plan, ClassPlan& c) {
     a.nrw = c.nrw;
     a.npb = c.npb;
     a.nllr = c.nllr;
-    a.gbase = c.gbase;
     a.hist_len = plan->hist_len;
     a.block = plan->prm.block;
     a.order = c.order;
@@ -341,8 +369,7 @@ int run_outer_all(t2s_plan* plan, int mode, hipStream_t st) {
 std::string sched_signature(const t2s_plan* plan, int mode) {
     std::string k = std::to_string(mode);
     for (const ClassPlan& c : plan->cls)
-        k += "/" + std::to_string(c.chunk) + "x" + std::to_string(c.nstreams) + "o" + std::to_string(c.order) + "g" +
-             std::to_string(c.gbase);
+        k += "/" + std::to_string(c.chunk) + "x" + std::to_string(c.nstreams) + "o" + std::to_string(c.order);
     return k;
 }
 
@@ -404,11 +431,126 @@ void residuals_from_hist(const double* h, double b0_norm, double* rp, double* rd
     *rd = den > 0 ? std::sqrt(h[1]) / den : 0.0;
 }
 
+// Stop / freeze decision of slice s of class c after its k-th outer iteration (k >= 1;
+// hs: the slice's history rows, b0_norm: ||b0||): stop when max(r_p, r_d) <= tol
+// (converged); otherwise, once k - 1 >= freeze_window, freeze the shift at draw k - 1
+// if the residual fell by less than freeze_stall over the last freeze_window outer
+// iterations.  A stopped slice is marked inactive on the device.
+int tol_decide(const t2s_params& prm, ClassPlan& c, int s, int k, const double* hs, double b0_norm, hipStream_t st,
+               bool* stop) {
+    double rp, rd;
+    residuals_from_hist(hs + (size_t)(k - 1) * 8, b0_norm, &rp, &rd);
+    const double r = std::max(rp, rd);
+    *stop = false;
+    if (r <= prm.tol) {
+        *stop = true;
+        c.converged[s] = 1;
+    } else if (c.k_freeze[s] < 0 && k - 1 >= prm.freeze_window) {
+        double rpo, rdo;
+        residuals_from_hist(hs + (size_t)(k - 1 - prm.freeze_window) * 8, b0_norm, &rpo, &rdo);
+        if (r > (1.0 - prm.freeze_stall) * std::max(rpo, rdo)) {
+            c.k_freeze[s] = k - 1;
+            HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 1, k - 1, -1, st));
+        }
+    }
+    if (*stop) HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 0, c.k_freeze[s], -1, st));
+    return 0;
+}
+
+// Copy the coil maps and samples of slices [first, first + count) of class c in, mark
+// them active with outer counter 0 and global indices gfirst.., and form b0 = A^H y
+// (projection, inverse column and row transforms, coil combine) and the initial
+// x = z = u = 0, r = b0 (with their partial sums).
+int load_range(ClassPlan& c, int first, int count, const void* sens, const void* ksp, hipMemcpyKind kind, int gfirst,
+               hipStream_t st) {
+    const size_t N = (size_t)c.ny * c.nz;
+    const ClassArgs& a = c.args;
+    const size_t ns = (size_t)count * c.C * c.M * N * 8, nk = (size_t)count * c.C * c.P * 8;
+    HIP_TRY(hipMemcpyAsync(a.sens + (size_t)first * c.C * c.M * N, sens, ns, kind, st));
+    if (nk) HIP_TRY(hipMemcpyAsync(a.ksp + (size_t)first * c.C * c.P, ksp, nk, kind, st));
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st, gfirst));
+    {
+        TIMED(T2S_KERNEL_LOAD);
+        HIP_CHECK_LAUNCH(t2s::launch_project(a, first, count, st));
+        HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_passC(a, first, count, 1, 0.0f, a.b0, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, nullptr, 0, st));
+    }
+    return 0;
+}
+
+// Load queued slices into the idle slots of the streaming class (ascending slots; a
+// run of consecutive idle slots takes consecutive slices of one queue entry in one
+// load), with the network warm start when one is set.
+int stream_refill(t2s_plan* plan, StreamState& q, ClassPlan& c, hipStream_t st) {
+    const size_t N = (size_t)c.ny * c.nz;
+    const size_t n = slice_images(c, plan->prm.K);
+    const ClassArgs& a = c.args;
+    int s = 0;
+    while (s < c.S) {
+        if (q.slots[s].item >= 0) {
+            ++s;
+            continue;
+        }
+        while (q.head < q.items.size() && q.items[q.head].next >= q.items[q.head].count) ++q.head;
+        if (q.head == q.items.size()) break;
+        StreamItem& it = q.items[q.head];
+        int r = 0;
+        while (s + r < c.S && q.slots[s + r].item < 0 && it.next + r < it.count) ++r;
+        const int j0 = it.next;
+        it.next += r;
+        if (int e = load_range(c, s, r, it.sens + (size_t)j0 * c.C * c.M * N * 8, it.ksp + (size_t)j0 * c.C * c.P * 8,
+                               hipMemcpyDeviceToDevice, it.g0 + j0, st))
+            return e;
+        q.loaded += r;
+        for (int i = 0; i < r; ++i) {
+            q.slots[s + i] = StreamSlot{(int)q.head, j0 + i, 0};
+            c.outer_run[s + i] = 0;
+            c.k_freeze[s + i] = -1;
+            c.converged[s + i] = 0;
+        }
+        if (q.net) {
+            // alpha0 = net(b0) straight into x, then r = b0 - A^H A alpha0 (t2s_set_initial)
+            for (int i = 0; i < r; i += q.net_batch) {
+                const int b = std::min(q.net_batch, r - i);
+                if (int e = t2s_unet_forward(q.net, a.b0 + (size_t)(s + i) * n, a.x + (size_t)(s + i) * n, b, st))
+                    return e;
+            }
+            if (int e = run_normal(a, s, r, a.x, 0, 0.0f, a.w, 0, st)) return e;
+            HIP_CHECK_LAUNCH(t2s::launch_init(a, s, r, a.x + (size_t)s * n, 1, st));
+        }
+        s += r;
+    }
+    return 0;
+}
+
+// Slot s finished its slice: result and report out, slot idle.
+int stream_complete(t2s_plan* plan, StreamState& q, ClassPlan& c, int s, const double* hist, double b0_norm,
+                    hipStream_t st) {
+    StreamSlot& sl = q.slots[s];
+    StreamItem& it = q.items[sl.item];
+    const size_t n = slice_images(c, plan->prm.K);
+    HIP_TRY(hipMemcpyAsync(it.out + (size_t)sl.j * n * 8, c.args.x + (size_t)s * n, n * 8, hipMemcpyDeviceToDevice,
+                           st));
+    if (it.rep) {
+        t2s_slice_report& r = it.rep[sl.j];
+        r.outer_iterations = sl.k;
+        r.k_freeze = c.k_freeze[s];
+        r.converged = c.converged[s];
+        r.r_primal = r.r_dual = std::numeric_limits<double>::quiet_NaN();
+        if (sl.k > 0 && sl.k <= plan->hist_len)
+            residuals_from_hist(hist + (size_t)(sl.k - 1) * 8, b0_norm, &r.r_primal, &r.r_dual);
+    }
+    sl.item = -1;
+    ++q.done;
+    return 0;
+}
+
 }  // namespace
 
 extern "C" {
 
-int t2s_version(void) { return 103; }
+int t2s_version(void) { return 104; }
 
 const char* t2s_last_error(void) { return g_err.c_str(); }
 
@@ -590,6 +732,7 @@ int t2s_plan_destroy(t2s_plan* plan) {
         for (hipEvent_t e : plan->ev_join) (void)hipEventDestroy(e);
         if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
         if (plan->cap) (void)hipStreamDestroy(plan->cap);
+        if (plan->stream.hpin) (void)hipHostFree(plan->stream.hpin);
     }
     delete plan;
     return 0;
@@ -650,7 +793,7 @@ int t2s_plan_bind_workspace(t2s_plan* plan, void* dev, size_t bytes, void* strea
         HIP_TRY(hipMemcpyAsync(b + c.o_rowptr, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(b + c.o_entt, c.ent_t.data(), c.ent_t.size() * 4, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(b + c.o_entp, c.ent_p.data(), c.ent_p.size() * 4, hipMemcpyHostToDevice, st));
-        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 0, -1, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 0, -1, 0, st, c.gbase));
         std::fill(c.loaded.begin(), c.loaded.end(), 0);
     }
     HIP_TRY(hipStreamSynchronize(st));   // host tables are pageable: finish before returning
@@ -677,18 +820,8 @@ int t2s_load_slices(t2s_plan* plan, int cls, int first, int count, const void* s
     }
     hipStream_t st = (hipStream_t)stream;
     const hipMemcpyKind kind = mem == T2S_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    const ClassArgs& a = c.args;
-    HIP_TRY(hipMemcpyAsync(a.sens + (size_t)first * c.C * c.M * N, sens, ns * 4, kind, st));
-    if (nk) HIP_TRY(hipMemcpyAsync(a.ksp + (size_t)first * c.C * c.P, ksp, nk * 4, kind, st));
-    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st));
-    {
-        g_prof = &plan->prof;
-        TIMED(T2S_KERNEL_LOAD);
-        HIP_CHECK_LAUNCH(t2s::launch_project(a, first, count, st));
-        HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, 0, st));
-        HIP_CHECK_LAUNCH(t2s::launch_passC(a, first, count, 1, 0.0f, a.b0, 0, st));
-        HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, nullptr, 0, st));
-    }
+    g_prof = &plan->prof;
+    if (int e = load_range(c, first, count, sens, ksp, kind, c.gbase + first, st)) return e;
     if (mem == T2S_HOST) HIP_TRY(hipStreamSynchronize(st));
     for (int i = 0; i < count; ++i) c.loaded[first + i] = 1;
     plan->last_stream = st;
@@ -714,7 +847,7 @@ int t2s_set_initial(t2s_plan* plan, int cls, int first, int count, const void* a
     const ClassArgs& a = c.args;
     float2* xs = a.x + (size_t)first * slice_images(c, K);
     HIP_TRY(hipMemcpyAsync(xs, alpha0, n * 4, mem == T2S_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
-    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st));
+    HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st, c.gbase + first));
     // r = b0 + rho z - (A^H A + rho) alpha0 with z = alpha0, u = 0  =>  r = b0 - A^H A alpha0
     if (int e = run_normal(a, first, count, a.x, 0, 0.0f, a.w, 0, st)) return e;
     HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, xs, 1, st));
@@ -738,7 +871,7 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
     for (const ClassPlan& c : plan->cls) maxns = std::max(maxns, c.nstreams);
     if (int e = ensure_streams(plan, maxns)) return e;
     for (ClassPlan& c : plan->cls) {
-        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, 0, st, c.gbase));
         std::fill(c.outer_run.begin(), c.outer_run.end(), 0);
         std::fill(c.k_freeze.begin(), c.k_freeze.end(), -1);
         std::fill(c.converged.begin(), c.converged.end(), 0);
@@ -795,26 +928,12 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream) {
                 for (int s = 0; s < c.S; ++s) {
                     if (!active[ci][s]) continue;
                     c.outer_run[s] = k;
-                    double rp, rd;
-                    const double* h = &hbuf[((size_t)s * plan->hist_len + (k - 1)) * 8];
-                    residuals_from_hist(h, b0norm[ci][s], &rp, &rd);
-                    const double r = std::max(rp, rd);
                     bool stop = false;
-                    if (r <= prm.tol) {
-                        stop = true;
-                        c.converged[s] = 1;
-                    } else if (c.k_freeze[s] < 0 && k - 1 >= prm.freeze_window) {
-                        double rpo, rdo;
-                        residuals_from_hist(&hbuf[((size_t)s * plan->hist_len + (k - 1 - prm.freeze_window)) * 8],
-                                            b0norm[ci][s], &rpo, &rdo);
-                        if (r > (1.0 - prm.freeze_stall) * std::max(rpo, rdo)) {
-                            c.k_freeze[s] = k - 1;
-                            HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 1, k - 1, -1, st));
-                        }
-                    }
+                    if (int e = tol_decide(prm, c, s, k, &hbuf[(size_t)s * plan->hist_len * 8], b0norm[ci][s], st,
+                                           &stop))
+                        return e;
                     if (stop) {
                         active[ci][s] = 0;
-                        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 0, c.k_freeze[s], -1, st));
                     } else {
                         any = true;
                     }
@@ -852,8 +971,9 @@ int t2s_set_slice_offset(t2s_plan* plan, int cls, int first_global) {
     if (!plan) return fail(T2S_EINVAL, "plan is NULL");
     if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
     if (first_global < 0) return fail(T2S_EINVAL, "first_global must be >= 0");
+    // kept on the host: the device-side global index of every slice is written from it
+    // when slices are loaded and when a solve starts
     plan->cls[cls].gbase = first_global;
-    plan->cls[cls].args.gbase = first_global;
     return 0;
 }
 
@@ -1099,7 +1219,7 @@ int t2s_fista(t2s_plan* plan, int mode, int n_iter, float step, void* stream) {
     const float tau = plan->prm.lambda * step;
     for (ClassPlan& c : plan->cls) {
         // every slice active, no frozen shift, iteration counter 0; momentum point y = x
-        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, 0, st));
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 1, -1, 0, st, c.gbase));
         const size_t n = slice_images(c, plan->prm.K);
         HIP_TRY(hipMemcpyAsync(c.args.z, c.args.x, (size_t)c.S * n * 8, hipMemcpyDeviceToDevice, st));
     }
@@ -1178,6 +1298,156 @@ int t2s_get_psi(const t2s_plan* plan, int cls, float* out) {
     if (!out) return fail(T2S_EINVAL, "out is NULL");
     const ClassPlan& c = plan->cls[cls];
     std::memcpy(out, c.psi.data(), c.psi.size() * 4);
+    return 0;
+}
+
+int t2s_stream_open(t2s_plan* plan, int cls, t2s_unet* net, int mode) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (plan->cls.size() != 1 || cls != 0) return fail(T2S_EINVAL, "streaming needs a one-class plan (cls 0)");
+    if (mode != T2S_BATCHED && mode != T2S_BATCHED_GRAPH) return fail(T2S_EINVAL, "mode must be BATCHED or BATCHED_GRAPH");
+    if (!plan->bound) return fail(T2S_ESTATE, "workspace not bound");
+    if (plan->prm.n_outer < 1) return fail(T2S_EINVAL, "streaming needs n_outer >= 1");
+    ClassPlan& c = plan->cls[cls];
+    int nb = 0;
+    if (net) {
+        int K = 0, H = 0, W = 0;
+        if (int e = t2s_unet_get_shape(net, &K, &nb, &H, &W)) return e;
+        if (K != plan->prm.K || H != c.ny || W != c.nz || c.M != 1)
+            return fail(T2S_ESHAPE, "network shape does not match the class (K, ny, nz, one map set)");
+    }
+    StreamState& q = plan->stream;
+    double* keep = q.hpin;
+    const size_t keep_len = q.hpin_len;
+    q = StreamState{};
+    q.hpin = keep;
+    q.hpin_len = keep_len;
+    const size_t need = (size_t)c.S * plan->hist_len * 8 + (size_t)c.S * c.nllr;
+    if (q.hpin_len < need) {
+        if (q.hpin) (void)hipHostFree(q.hpin);
+        q.hpin = nullptr;
+        q.hpin_len = 0;
+        HIP_TRY(hipHostMalloc((void**)&q.hpin, need * sizeof(double), hipHostMallocDefault));
+        q.hpin_len = need;
+    }
+    q.open = q.fresh = true;
+    q.cls = cls;
+    q.mode = mode;
+    q.net = net;
+    q.net_batch = nb;
+    q.slots.assign(c.S, StreamSlot{});
+    std::fill(c.loaded.begin(), c.loaded.end(), 0);   // t2s_reconstruct needs fresh loads afterwards
+    return 0;
+}
+
+int t2s_stream_submit(t2s_plan* plan, int count, int first_global, const void* sens, const void* ksp,
+                      void* alpha_out, t2s_slice_report* reports) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    if (!plan->stream.open) return fail(T2S_ESTATE, "stream not open");
+    if (count < 1 || first_global < 0) return fail(T2S_EINVAL, "count must be >= 1, first_global >= 0");
+    if (!sens || !ksp || !alpha_out) return fail(T2S_EINVAL, "sens, ksp or alpha_out is NULL");
+    StreamItem it;
+    it.count = count;
+    it.g0 = first_global;
+    it.sens = (const char*)sens;
+    it.ksp = (const char*)ksp;
+    it.out = (char*)alpha_out;
+    it.rep = reports;
+    plan->stream.items.push_back(it);
+    return 0;
+}
+
+int t2s_stream_run(t2s_plan* plan, int min_done, t2s_stream_status* status, void* stream) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    StreamState& q = plan->stream;
+    if (!q.open) return fail(T2S_ESTATE, "stream not open");
+    hipStream_t st = (hipStream_t)stream;
+    plan->last_stream = st;
+    g_prof = &plan->prof;
+    ClassPlan& c = plan->cls[q.cls];
+    const t2s_params& prm = plan->prm;
+    const bool tolmode = prm.tol > 0;
+    // outer iterations between decisions (in fixed-iteration mode a slot stops at n_outer only)
+    const int ce = tolmode ? prm.check_every : prm.n_outer;
+    if (q.fresh) {
+        HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, 0, c.S, 0, -1, 0, st));   // every slot idle
+        q.fresh = false;
+    }
+    if (int e = ensure_streams(plan, c.nstreams)) return e;
+    const bool use_graph = q.mode == T2S_BATCHED_GRAPH && !plan->prof.on;
+    if (use_graph) {
+        if (int e = ensure_graph(plan, T2S_BATCHED_GRAPH)) return e;
+    }
+    const size_t hn = (size_t)c.S * plan->hist_len * 8;
+    double* hist = q.hpin;
+    double* b0p = q.hpin + hn;
+    const long done0 = q.done;
+    int warn = 0;
+    for (;;) {
+        if (int e = stream_refill(plan, q, c, st)) return e;
+        int chunk = ce, nact = 0;
+        for (const StreamSlot& sl : q.slots) {
+            if (sl.item < 0) continue;
+            ++nact;
+            chunk = std::min(chunk, std::min(ce - sl.k % ce, prm.n_outer - sl.k));
+        }
+        if (nact == 0) break;
+        q.slice_outer += (int64_t)nact * chunk;
+        for (int i = 0; i < chunk; ++i) {
+            if (use_graph) {
+                HIP_TRY(hipGraphLaunch(plan->gexec, st));
+            } else if (int e = run_outer_all(plan, T2S_BATCHED, st)) {
+                return e;
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(hist, c.args.hist, hn * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(b0p, c.args.b0n, (size_t)c.S * c.nllr * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int s = 0; s < c.S; ++s) {
+            StreamSlot& sl = q.slots[s];
+            if (sl.item < 0) continue;
+            sl.k += chunk;
+            c.outer_run[s] = sl.k;
+            double bb = 0.0;
+            for (int j = 0; j < c.nllr; ++j) bb += b0p[(size_t)s * c.nllr + j];
+            const double b0_norm = std::sqrt(bb);
+            const double* hs = hist + (size_t)s * plan->hist_len * 8;
+            bool stop = false;
+            if (tolmode && (sl.k % ce == 0 || sl.k >= prm.n_outer)) {
+                if (int e = tol_decide(prm, c, s, sl.k, hs, b0_norm, st, &stop)) return e;
+            }
+            if (!stop && sl.k >= prm.n_outer) {
+                stop = true;
+                if (tolmode) warn = T2S_WNOTCONVERGED;
+                HIP_CHECK_LAUNCH(t2s::launch_set_state(c.args, s, 1, 0, c.k_freeze[s], -1, st));
+            }
+            if (stop) {
+                if (int e = stream_complete(plan, q, c, s, hs, b0_norm, st)) return e;
+            }
+        }
+        if (min_done > 0 && q.done - done0 >= min_done) break;
+    }
+    plan->reconstructed = true;
+    if (status) {
+        long f = 0;
+        for (const StreamSlot& sl : q.slots) f += sl.item >= 0;
+        for (size_t i = q.head; i < q.items.size(); ++i) f += q.items[i].count - q.items[i].next;
+        status->done = (int)q.done;
+        status->in_flight = (int)f;
+        status->loaded = q.loaded;
+        status->slice_outer = q.slice_outer;
+    }
+    if (warn) return fail(warn, "tolerance not met by n_outer for some slices");
+    return 0;
+}
+
+int t2s_stream_close(t2s_plan* plan) {
+    if (!plan) return fail(T2S_EINVAL, "plan is NULL");
+    StreamState& q = plan->stream;
+    q.open = false;
+    q.items.clear();
+    q.slots.clear();
+    q.head = 0;
+    q.net = nullptr;
     return 0;
 }
 

@@ -26,7 +26,6 @@ struct ClassArgs {
     int nrw, npb, nllr;          // partial-sum counts per slice: row-pass workgroups (passes A
                                  // and C: ny / kRowTile * K), pass-B workgroups, LLR workgroups
                                  // (M runs, one per map set)
-    int gbase;                   // global index of the class's slice 0
     int hist_len;                // outer-iteration capacity of the residual history
     int block;                   // LLR block edge
     int order;                   // workgroup order of the row passes: bit 0 pass A, bit 1
@@ -54,7 +53,8 @@ struct ClassArgs {
     double* b0n;                 // [S][nllr]   ||b0||^2 partials (written with the state init)
     double* llr;                 // [S][nllr][8] residual partial sums of the z-step
     double* hist;                // [S][hist_len][8] per-outer residual sums
-    int* state;                  // [S][4]: active flag, frozen outer index (-1: none), outer counter, spare
+    int* state;                  // [S][4]: active flag, frozen outer index (-1: none), outer counter,
+                                 // global slice index (the block-shift schedule's g)
 };
 
 constexpr int kOrderXcdA = 1;
@@ -105,9 +105,10 @@ hipError_t launch_backproject(const ClassArgs& a, int s0, int count, int nte, co
 hipError_t launch_readout_ifft(int nx, int C, int P, const float2* in, float2* out, hipStream_t st);
 // v[s] /= sqrt(sum of the pass-A partials pa[s]) for slices [s0, s0 + count)
 hipError_t launch_normalize(const ClassArgs& a, int s0, int count, float2* v, hipStream_t st);
-// state[s] = (active, frozen[, counter = kreset if kreset >= 0]) for slices [s0, s0 + count)
+// state[s] = (active, frozen[, counter = kreset if kreset >= 0][, global index = gfirst + s - s0
+// if gfirst >= 0]) for slices [s0, s0 + count)
 hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, int kreset,
-                            hipStream_t st);
+                            hipStream_t st, int gfirst = -1);
 // hist[s][counter] = sum of the LLR partials of slice s; counter += 1
 hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, hipStream_t st);
 

@@ -1035,6 +1035,15 @@ int t2s_unet_param_count(const t2s_unet* u, size_t* n) {
     return 0;
 }
 
+int t2s_unet_get_shape(const t2s_unet* u, int* K, int* max_batch, int* H, int* W) {
+    if (!u) return ufail(T2S_EINVAL, "NULL argument");
+    if (K) *K = u->K;
+    if (max_batch) *max_batch = u->maxB;
+    if (H) *H = u->H;
+    if (W) *W = u->W;
+    return 0;
+}
+
 int t2s_unet_workspace_bytes(const t2s_unet* u, size_t* bytes) {
     if (!u || !bytes) return ufail(T2S_EINVAL, "NULL argument");
     *bytes = u->bytes;

@@ -8,8 +8,9 @@
     # per-kernel-family averages and utilisation metrics of one or more counter runs
     python -m paper_1809_04195_amd.prof_summary counters DIR [DIR ...]
 
-    # markdown table of a --kernel-trace --stats summary
-    python -m paper_1809_04195_amd.prof_summary stats DIR
+    # markdown table of a --kernel-trace --stats run (csv or rocpd database output),
+    # optionally from the N-th dispatch of a named kernel on (the timed region)
+    python -m paper_1809_04195_amd.prof_summary stats DIR [--after k_project:2]
 
 DIR is a rocprofv3 output directory (or the CSV file itself).  Utilisation metrics
 follow rocprofv3's own derived-metric definitions on MI355X (256 CUs, 1024 SIMDs,
@@ -176,14 +177,39 @@ def counters(args):
         print(f"| {f} | {n} | {us:.1f} | " + " | ".join(f"{m[k]:.2f}" if k in m else "" for k in keys) + " |")
 
 
+def _stats_rows(path, after=""):
+    """[(name, calls, total ns, average ns, percent)] of a --kernel-trace --stats run:
+    its kernel_stats.csv (csv output) or its rocpd database (the default output).
+    after = "NAME:N" keeps the dispatches from the N-th dispatch of a kernel whose name
+    contains NAME on (database output only): the timed region of a run."""
+    dbs = sorted(glob.glob(os.path.join(path, "**", "*.db"), recursive=True)) if os.path.isdir(path) else (
+        [path] if path.endswith(".db") else [])
+    if not dbs:
+        if after:
+            raise ValueError("--after needs the rocpd database output")
+        return [(r["Name"], int(r["Calls"]), int(r["TotalDurationNs"]), float(r["AverageNs"]),
+                 float(r["Percentage"])) for r in csv.DictReader(open(_csv(path, "kernel_stats.csv")))]
+    import sqlite3
+    db = sqlite3.connect(dbs[0])
+    t0 = 0
+    if after:
+        key, n = after.rsplit(":", 1)
+        starts = [r[0] for r in db.execute("select start from kernels where instr(name, ?) > 0 order by start",
+                                           (key,))]
+        if len(starts) < int(n):
+            raise ValueError(f"fewer than {n} dispatches of {key}")
+        t0 = starts[int(n) - 1]
+    rows = list(db.execute("select name, count(*), sum(end - start) from kernels where start >= ? group by name "
+                           "order by sum(end - start) desc", (t0,)))
+    tot = sum(r[2] for r in rows) or 1
+    return [(n, c, t, t / c, 100.0 * t / tot) for n, c, t in rows]
+
+
 def stats(args):
-    path = _csv(args.dir, "kernel_stats.csv")
-    rows = list(csv.DictReader(open(path)))
     print("| kernel | calls | total (ns) | average (ns) | % |")
     print("|---|---|---|---|---|")
-    for r in rows:
-        print(f"| `{r['Name'][:90]}` | {r['Calls']} | {r['TotalDurationNs']} | {float(r['AverageNs']):.0f} | "
-              f"{float(r['Percentage']):.2f} |")
+    for name, calls, total, avg, pct in _stats_rows(args.dir, args.after):
+        print(f"| `{name[:90]}` | {calls} | {total} | {avg:.0f} | {pct:.2f} |")
 
 
 def main():
@@ -200,6 +226,7 @@ def main():
     c.add_argument("dirs", nargs="+")
     s = sub.add_parser("stats")
     s.add_argument("dir")
+    s.add_argument("--after", default="", help="NAME:N: from the N-th dispatch of a kernel named *NAME* on")
     args = ap.parse_args()
     {"traffic": traffic, "counters": counters, "stats": stats}[args.cmd](args)
 

@@ -314,3 +314,44 @@ def test_paper_grid_two_map_sets_and_twelve_point_blocks_accepted():
     tiles = T.t2s_plan_workspace_bytes(h)
     T.t2s_plan_destroy(h)
     assert tiles >= 7 * 4 * 240 * 272 * 8
+
+
+def test_stream_validation_without_gpu():
+    """Streaming entry points check their arguments and the plan state before any HIP call."""
+    L = T.lib()
+    phi = _phi()
+    cls, masks = _classes()
+    assert L.t2s_stream_open(None, 0, None, T.T2S_BATCHED) == T.T2S_EINVAL
+    assert L.t2s_stream_submit(None, 1, 0, None, None, None, None) == T.T2S_EINVAL
+    assert L.t2s_stream_run(None, 0, None, None, None) == T.T2S_EINVAL
+    assert L.t2s_stream_close(None) == T.T2S_EINVAL
+    code, h = _create(phi, cls)
+    assert code == 0
+    buf = np.zeros(10, np.complex64)
+    # not open: submit / run are state errors
+    assert L.t2s_stream_submit(h, 1, 0, buf.ctypes.data, buf.ctypes.data, buf.ctypes.data, None) == T.T2S_ESTATE
+    assert L.t2s_stream_run(h, 0, None, None, None) == T.T2S_ESTATE
+    # bad class / mode, then the unbound workspace
+    assert L.t2s_stream_open(h, 1, None, T.T2S_BATCHED) == T.T2S_EINVAL
+    assert L.t2s_stream_open(h, 0, None, T.T2S_PER_SLICE) == T.T2S_EINVAL
+    assert L.t2s_stream_open(h, 0, None, T.T2S_BATCHED) == T.T2S_ESTATE
+    assert L.t2s_stream_close(h) == 0
+    assert L.t2s_plan_destroy(h) == 0
+    # two shape classes: streaming needs a one-class plan
+    cls2 = cls + [(32, 32, 2, 1, masks[:, :32, :32].copy())]
+    code, h = _create(phi, cls2)
+    assert code == 0
+    assert L.t2s_stream_open(h, 0, None, T.T2S_BATCHED) == T.T2S_EINVAL
+    assert L.t2s_plan_destroy(h) == 0
+
+
+def test_unet_get_shape_without_gpu():
+    h = ctypes.c_void_p()
+    L = T.lib()
+    assert L.t2s_unet_create(5, 16, 3, 4, 32, 48, ctypes.byref(h)) == 0
+    K, B, H, W = (ctypes.c_int() for _ in range(4))
+    assert L.t2s_unet_get_shape(h, ctypes.byref(K), ctypes.byref(B), ctypes.byref(H), ctypes.byref(W)) == 0
+    assert (K.value, B.value, H.value, W.value) == (5, 4, 32, 48)
+    assert L.t2s_unet_get_shape(h, None, None, None, None) == 0
+    assert L.t2s_unet_get_shape(None, None, None, None, None) == T.T2S_EINVAL
+    assert L.t2s_unet_destroy(h) == 0
