@@ -10,14 +10,12 @@ The volume is streamed through a plan of --slots slices (continuous batching,
 t2s_stream_*): every slot holds one slice; at each stop decision the slots whose
 slice stopped take the next slices of the volume (projection + adjoint of the
 device-resident samples, the warm-start network on b0 = A^H y, the warm start), so
-every launch carries a full set of slices.  One step = the solver running until a
-fixed number of further slices have completed (the volume is queued repeatedly, each
-slice with its own global index, so its block shifts are those of a whole-volume
-run); the warm-up steps fill the slots, so the timed steps measure the steady state.  Slices per step =
-ceil(512 / steps) by default, so the timed steps cover one volume's worth of slices
-(its edge slices stop within a few outer iterations, its central ones take hundreds:
-a window of part of a volume would be biased either way).  `value` is completed
-slices/s over the timed steps; s/volume = 512 / value.
+launches carry a full set of slices until the queue runs dry.  The timed region is
+one whole volume, from empty slots to its last slice (every slice counted once, its
+block shifts those of its global index): `steps` steps of ceil(512 / steps) completed
+slices, the last one running until every slice has stopped.  The untimed warm-up
+streams the first warmup x ceil(512 / steps) slices to completion.  `value` is
+512 / the volume's time (slices/s); s/volume is that time.
 
 Beside it, measured in the same run on two sampled batches of 32 slices: the plain
 solver (one launch sequence per slice, cold start, same tolerance), the batched
@@ -131,24 +129,29 @@ def roofline_from(prof, alg):
                 frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=None,
                 avg_launch_ms=round(kd["avg_ms"], 4), alg_bytes_per_launch=int(kd["alg_bytes_per_launch"]))
     short = {k: dict(launches=v["launches"], avg_ms=round(v["avg_ms"], 4),
+                     alg_bytes_per_launch=None if v["alg_bytes_per_launch"] is None else int(v["alg_bytes_per_launch"]),
                      achieved_gbs=None if v["achieved_gbs"] is None else round(v["achieved_gbs"], 1))
              for k, v in kern.items()}
     return roof, short
 
 
 def counter_traffic(path, workload, kernel):
-    """HBM bytes per launch of `kernel` from a committed counter summary, if it was taken
-    on the current kernel source and this workload (else None)."""
+    """(HBM bytes per launch, their ratio to the algorithmic bytes of the same launches)
+    of `kernel` from a committed counter summary, if it was taken on the current kernel
+    source and this workload (else (None, None))."""
     import hashlib
     if not path or not os.path.exists(path):
-        return None
+        return None, None
     tr = json.load(open(path))
     src = os.path.join(ROOT, "paper_1809_04195_amd", "csrc", "kernels.hip")
     cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if tr.get("kernels_source_sha256_16") != cur or tr.get("workload") != workload:
-        return None
+        return None, None
     t = tr["traffic"].get(kernel)
-    return None if t is None else int(t["bytes_per_launch"])
+    if t is None:
+        return None, None
+    r = t.get("ratio_to_alg")
+    return int(t["bytes_per_launch"]), None if r is None else round(r, 3)
 
 
 # ---------------------------------------------------------------------------
@@ -178,10 +181,11 @@ def fixed_vol320(T, torch, d, steps):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = {name: T.t2s_profile_read(plan.handle, k) for k, name in enumerate(T.KERNEL_NAMES)}
+    T.t2s_profile_enable(plan.handle, False)
     alg = solve_bytes(cl.ny, cl.nz, cl.ncoils, phi.shape[1], cfg["n_cg"], cfg["n_outer"] * cl.nslices * steps, 0)
     roof, kern = roofline_from(prof, alg)
-    roof["traffic"] = counter_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_vol320_256x256_c8_t80_k4.json"),
-                                      cfg["name"], roof["kernel"])
+    roof["traffic"], roof["traffic_vs_alg"] = counter_traffic(
+        os.path.join(ROOT, "profiles", "hbm_traffic_vol320_256x256_c8_t80_k4.json"), cfg["name"], roof["kernel"])
     plan.close()
     return dict(workload=cfg["name"], schedule="100 outer x 5 CG, batched", slices_per_s=round(
         cl.nslices * steps / el, 2), s_per_volume=round(el / steps, 4), roofline=roof, kernels=kern)
@@ -200,9 +204,14 @@ def main():
                     help="slices completed per step (0: ceil(volume / steps), so that the timed steps cover one "
                          "volume and its mix of easy and hard slices)")
     ap.add_argument("--slots", type=int, default=256, help="slices the streaming plan holds at once")
+    ap.add_argument("--queue-order", choices=("index", "energy"), default="index",
+                    help="order the volume's slices are queued in: slice index, or descending sample energy (a "
+                         "longest-first guess; it measured no faster on this volume)")
     ap.add_argument("--schedule", type=str, default="0,1",
                     help="CHUNK,STREAMS of the pass launches (0,1: all slots per launch on one stream, so every "
                          "kernel event times one whole launch), or 'auto' (the autotuner)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the classes' default kernel schedule flags (short counter runs under rocprofv3)")
     ap.add_argument("--plain-batches", type=str, default="4,11",
                     help="batches (of --batch slices) run with the plain, the batched and the streamed solver")
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: min(16, cores))")
@@ -258,6 +267,7 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    log("copying the volume's coil maps and samples to the GPU")
     dsens = torch.from_numpy(cl.sens).to(dev)
     dksp = torch.from_numpy(cl.ksp).to(dev)
     torch.cuda.synchronize()
@@ -270,16 +280,18 @@ def main():
                       seed=cfg["seed"], **TOL_KW)
 
     def tune(plan, n):
-        # schedule: autotuned (chunking over streams, workgroup order) or fixed; the
-        # workgroup order is always tuned (on the first n slices, loaded for it)
-        T.t2s_load_slices(plan.handle, 0, 0, n, dsens[:n], dksp[:n], stream)
-        T.t2s_autotune(plan.handle, 2, stream)
+        # schedule: autotuned (chunking over streams, kernel schedule flags) or fixed; the
+        # flags are tuned unless --no-autotune (on the first n slices, loaded for it)
+        if not args.no_autotune:
+            T.t2s_load_slices(plan.handle, 0, 0, n, dsens[:n], dksp[:n], stream)
+            T.t2s_autotune(plan.handle, 2, stream)
         if args.schedule != "auto":
             ch, ns = (int(v) for v in args.schedule.split(","))
             T.t2s_set_schedule(plan.handle, 0, ch, ns)
         return T.t2s_get_schedule(plan.handle, 0), T.t2s_get_order(plan.handle, 0)
 
     bplan, splan = make_plan(B), make_plan(P)
+    log("plans bound; " + ("fixed schedule" if args.no_autotune else "autotuning"))
     t1 = time.perf_counter()
     tune(bplan, B)
     sched, order = tune(splan, P)
@@ -343,40 +355,51 @@ def main():
         del ca, cb
         log("copy probe: 1 GiB read + 1 GiB write")
 
-    # the volume, queued often enough for the warm-up and timed steps
+    # warm-up (untimed): the first warmup x D slices of the volume streamed to completion
     out_vol = torch.empty((S, K, cl.ny, cl.nz), dtype=torch.complex64, device=dev)
+    nw = min(S, args.warmup * D)
+    if nw:
+        splan.stream_open(net, T.T2S_BATCHED)
+        splan.stream_submit(dsens[:nw], dksp[:nw], out_vol[:nw], 0)
+        for i in range(args.warmup):
+            _, st = splan.stream_run(D if i + 1 < args.warmup else 0)
+            torch.cuda.synchronize()
+            log(f"warmup step {i + 1}/{args.warmup}: {st['done']} of {nw} slices completed")
+    # timed: the whole volume, from empty slots to its last slice, in `steps` steps of D
+    # completed slices (the last step runs until every slice has stopped)
     splan.stream_open(net, T.T2S_BATCHED)
-    reps_needed = ((args.warmup + args.steps) * D + P + S - 1) // S + 1
-    for _ in range(reps_needed):
-        splan.stream_submit(dsens, dksp, out_vol, 0)
-    st = dict(done=0, in_flight=0, loaded=0, slice_outer=0)
-    for i in range(args.warmup):
-        _, st = splan.stream_run(D)
-        torch.cuda.synchronize()
-        log(f"warmup step {i + 1}/{args.warmup}: {st['done']} slices completed")
+    if args.queue_order == "energy":
+        # longest first: slices in descending order of their sample energy ||y||, a cost
+        # proxy (slices without signal stop at the first check, the central ones take the
+        # most outer iterations), so the volume does not end on its hardest slices
+        energy = torch.linalg.vector_norm(dksp.reshape(S, -1), dim=1)
+        queue = torch.argsort(energy, descending=True).cpu().numpy()
+    else:
+        queue = np.arange(S)
+    rep = [splan.stream_submit(dsens[g:g + 1], dksp[g:g + 1], out_vol[g:g + 1], int(g)) for g in queue]
     T.t2s_profile_enable(splan.handle, True)
     torch.cuda.synchronize()
-    st0 = st
+    st = dict(done=0, in_flight=S, loaded=0, slice_outer=0)
     t0 = time.perf_counter()
     for i in range(args.steps):
-        # completions come in bursts at the stop decisions: aim every step at its share
-        # of the window so that the timed steps together cover steps x D slices
-        need = (i + 1) * D - (st["done"] - st0["done"])
-        code, st = splan.stream_run(max(need, 1))
+        code, st = splan.stream_run(max(1, (i + 1) * D - st["done"]) if i + 1 < args.steps else 0)
         torch.cuda.synchronize()
-        log(f"timed step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s: {st['done'] - st0['done']} "
-            f"slices completed, {st['in_flight']} in flight or queued")
+        log(f"timed step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s: {st['done']} of {S} slices "
+            f"completed")
+        if st["in_flight"] == 0:
+            break
     elapsed = time.perf_counter() - t0
+    assert st["done"] == S and st["in_flight"] == 0, st
     prof = {name: T.t2s_profile_read(splan.handle, k) for k, name in enumerate(T.KERNEL_NAMES)}
     T.t2s_profile_enable(splan.handle, False)
     splan.stream_close()
-    slices_done = st["done"] - st0["done"]
-    slice_outer = st["slice_outer"] - st0["slice_outer"]
-    loads = st["loaded"] - st0["loaded"]
+    reps_vol = [T.Plan.stream_reports(r)[0] for r in rep]
+    outer_vol = [r["outer_iterations"] for r in reps_vol]
+    slices_done, slice_outer, loads = S, st["slice_outer"], st["loaded"]
     value = slices_done / elapsed
     alg = solve_bytes(cl.ny, cl.nz, cl.ncoils, K, ncg, slice_outer, loads)
     roof, kern = roofline_from(prof, alg)
-    roof["traffic"] = counter_traffic(args.traffic, cfg["name"], roof["kernel"])
+    roof["traffic"], roof["traffic_vs_alg"] = counter_traffic(args.traffic, cfg["name"], roof["kernel"])
     solver_bytes = sum(alg.values())
 
     comp = None
@@ -429,15 +452,18 @@ def main():
                    "coils": cl.ncoils, "grid": [cl.ny, cl.nz], "tol": cfg["tol"], "outer_cap": cfg["n_outer"],
                    "cg": ncg, "block": cfg["block"], "lambda": cfg["lam"], "rho": cfg["rho"],
                    "start": "warm (U-Net on b0)",
-                   "mode": f"streamed through {P} slots (continuous batching, kernel events)",
-                   "step": f"{D} more slices completed: refills (load + U-Net + warm start) and outer iterations "
-                           "to tolerance",
+                   "mode": f"streamed through {P} slots (continuous batching, kernel events), queued by "
+                           f"{'descending sample energy' if args.queue_order == 'energy' else 'slice index'}",
+                   "step": f"{D} more slices of the volume completed (the last step: the rest): refills (load + "
+                           "U-Net + warm start) and outer iterations to tolerance",
                    "comparison_batch": B,
                    "schedule": list(sched), "order": order},
         "roofline": roof,
         "solver_alg_gbs": round(solver_bytes / (elapsed * 1e9), 1),
         "slices_completed": slices_done,
-        "mean_outer_warm": round(slice_outer / max(slices_done, 1), 1),
+        "mean_outer_warm": round(float(np.mean(outer_vol)), 1),
+        "max_outer_warm": int(max(outer_vol)),
+        "converged": int(sum(r["converged"] for r in reps_vol)),
         "kernels": kern,
         "comparison": comp,
         "vol320_fixed": extra,

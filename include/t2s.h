@@ -197,12 +197,20 @@ int t2s_reconstruct(t2s_plan* plan, int mode, void* stream);
 int t2s_set_schedule(t2s_plan* plan, int cls, int chunk, int nstreams);
 int t2s_get_schedule(const t2s_plan* plan, int cls, int* chunk, int* nstreams);
 
-/* Workgroup order of the row passes of class `cls`: with T2S_ORDER_XCD_PASS_A
- * (T2S_ORDER_XCD_PASS_C) the workgroups of pass A (C) are dealt to the device's 8
- * XCDs in contiguous runs of row tiles instead of round-robin.  Which streams
- * better depends on the shape; same arithmetic, bitwise identical results. */
+/* Kernel schedule flags of class `cls` (the passes of Alg. 1, Sec. IV-B):
+ * T2S_ORDER_XCD_PASS_A (T2S_ORDER_XCD_PASS_C): the workgroups of pass A (C) are dealt
+ * to the device's 8 XCDs in contiguous runs of row tiles instead of round-robin;
+ * T2S_ORDER_XCD_PASS_B: pass B's workgroups go coil-fastest in contiguous runs, so the
+ * coils of a column tile share its Psi entries in one XCD's L2;
+ * T2S_ORDER_PASS_C_LDS2: pass C double-buffers its LDS exchange (one barrier per coil
+ * instead of two; row lengths >= 256, ignored below).  A new class starts with
+ * T2S_ORDER_XCD_PASS_B when its Psi table exceeds 2 MB and T2S_ORDER_PASS_C_LDS2 from
+ * 384 points; t2s_autotune times every combination.  Which runs faster depends on the
+ * shape; same arithmetic, bitwise identical results.  Errors: T2S_EINVAL. */
 #define T2S_ORDER_XCD_PASS_A 1
 #define T2S_ORDER_XCD_PASS_C 2
+#define T2S_ORDER_XCD_PASS_B 4
+#define T2S_ORDER_PASS_C_LDS2 8
 int t2s_set_order(t2s_plan* plan, int cls, int order);
 
 /* Global index of class `cls`'s slice 0 in the block-shift schedule (default: the
@@ -215,7 +223,8 @@ int t2s_get_order(const t2s_plan* plan, int cls, int* order);
 
 /* Pick every class's schedule by timing `reps` CG steps of passes A/B/C per
  * candidate (all slices at once; chunks of 32/16/8/4/2 slices over 1, 2 or 4
- * streams; then the workgroup orders of t2s_set_order with the best of those) on
+ * streams; then every combination of the kernel schedule flags of t2s_set_order with
+ * the best of those) on
  * the loaded slices, on `stream`.  Results are cached per process by (ny, nz,
  * ncoils, K, slices, device architecture).  Solver state is untouched.
  * Synchronises `stream`. */
@@ -330,7 +339,9 @@ int t2s_get_psi(const t2s_plan* plan, int cls, float* out);
 #define T2S_KERNEL_LOAD 4      /* projection + adjoint of load_slices               */
 #define T2S_KERNEL_COUNT 5
 
-/* Enable (1) or disable (0) event timing of every launch; enabling clears the totals. */
+/* Enable (1) or disable (0) event timing of every launch; enabling clears the totals.
+ * With a bound workspace each call also launches an empty kernel (k_profile_mark) on
+ * the plan's last stream, so a kernel trace can cut out the launches that were timed. */
 int t2s_profile_enable(t2s_plan* plan, int enable);
 
 /* Launch count and summed duration (ms) of kernel family `kernel` since the last
@@ -407,8 +418,10 @@ int t2s_unet_get_shape(const t2s_unet* net, int* K, int* max_batch, int* H, int*
  * iterations.  Instead of solving fixed batches, whose launches thin out as slices
  * stop, a one-class plan's S slices become slots fed from a queue of slices: at every
  * stop decision (each check_every outer iterations of a slot) the slots whose slice
- * stopped are refilled with the next queued slices (load: projection and adjoint;
- * optional network warm start; then the slot joins the next outer iteration).  Every
+ * stopped are refilled with the next queued slices in queue order (load: projection
+ * and adjoint; optional network warm start; then the slot joins the next outer
+ * iteration), so a caller that queues its most expensive slices first keeps the end of
+ * a volume from waiting on them.  Every
  * slice runs exactly the arithmetic, stop and freeze decisions it has in
  * t2s_reconstruct (its own outer counter from 0, its own global index in the shift
  * schedule), so results equal those of a batch solve of the same slices.
@@ -452,8 +465,11 @@ int t2s_stream_run(t2s_plan* plan, int min_done, t2s_stream_status* status, void
 int t2s_stream_close(t2s_plan* plan);
 
 /* One 16x16x16 bf16 matrix-core product D = A B (host fp32 row-major, rounded to bf16
- * on input) -- a check of the lane layout the convolution kernels assume. */
+ * on input) -- a check of the lane layout the weight-gradient kernels assume. */
 int t2s_unet_mfma_probe(const float* A, const float* B, float* D);
+/* The same for the 32-deep product of the convolution kernels: A [16][32], B [32][16],
+ * D [16][16] host fp32 row-major (A and B rounded to bf16). */
+int t2s_unet_mfma_probe32(const float* A, const float* B, float* D);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the product of t2s_unet_mfma_probe

@@ -43,6 +43,8 @@ T2S_KERNEL_PASS_B = 1
 T2S_KERNEL_PASS_C = 2
 T2S_ORDER_XCD_PASS_A = 1
 T2S_ORDER_XCD_PASS_C = 2
+T2S_ORDER_XCD_PASS_B = 4
+T2S_ORDER_PASS_C_LDS2 = 8
 T2S_KERNEL_LLR = 3
 T2S_KERNEL_LOAD = 4
 KERNEL_NAMES = ("pass_a", "pass_b", "pass_c", "llr_admm", "load_adjoint")
@@ -174,6 +176,8 @@ _SIGS = {
                                 ctypes.POINTER(ctypes.c_int), ctypes.c_void_p], ctypes.c_int),
     "t2s_unet_mfma_probe": ([ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "t2s_unet_mfma_probe32": ([ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                               ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "t2s_unet_mfma_probe_static": ([ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                     ctypes.POINTER(ctypes.c_float), ctypes.c_int], ctypes.c_int),
     "t2s_block_shift": ([ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -553,6 +557,17 @@ def t2s_unet_mfma_probe(A, B):
     B = np.ascontiguousarray(B, dtype=np.float32)
     D = np.empty((16, 16), dtype=np.float32)
     _check(lib().t2s_unet_mfma_probe(_fptr(A), _fptr(B), _fptr(D)))
+    return D
+
+
+def t2s_unet_mfma_probe32(A, B):
+    """D = A B for A [16, 32], B [32, 16] through the 32-deep bf16 matrix-core product."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    if A.shape != (16, 32) or B.shape != (32, 16):
+        raise ValueError("A must be [16, 32] and B [32, 16]")
+    D = np.empty((16, 16), dtype=np.float32)
+    _check(lib().t2s_unet_mfma_probe32(_fptr(A), _fptr(B), _fptr(D)))
     return D
 
 

@@ -461,27 +461,42 @@ int tol_decide(const t2s_params& prm, ClassPlan& c, int s, int k, const double* 
 // them active with outer counter 0 and global indices gfirst.., and form b0 = A^H y
 // (projection, inverse column and row transforms, coil combine) and the initial
 // x = z = u = 0, r = b0 (with their partial sums).
-int load_range(ClassPlan& c, int first, int count, const void* sens, const void* ksp, hipMemcpyKind kind, int gfirst,
-               hipStream_t st) {
+// Copy the coil maps and samples of `count` slices into slices first.. of class c and
+// mark them active with outer counter 0 and global indices gfirst, gfirst + 1, ...
+int load_copy(ClassPlan& c, int first, int count, const void* sens, const void* ksp, hipMemcpyKind kind, int gfirst,
+              hipStream_t st) {
     const size_t N = (size_t)c.ny * c.nz;
     const ClassArgs& a = c.args;
     const size_t ns = (size_t)count * c.C * c.M * N * 8, nk = (size_t)count * c.C * c.P * 8;
     HIP_TRY(hipMemcpyAsync(a.sens + (size_t)first * c.C * c.M * N, sens, ns, kind, st));
     if (nk) HIP_TRY(hipMemcpyAsync(a.ksp + (size_t)first * c.C * c.P, ksp, nk, kind, st));
     HIP_CHECK_LAUNCH(t2s::launch_set_state(a, first, count, 1, -1, 0, st, gfirst));
-    {
-        TIMED(T2S_KERNEL_LOAD);
-        HIP_CHECK_LAUNCH(t2s::launch_project(a, first, count, st));
-        HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, 0, st));
-        HIP_CHECK_LAUNCH(t2s::launch_passC(a, first, count, 1, 0.0f, a.b0, 0, st));
-        HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, nullptr, 0, st));
-    }
     return 0;
 }
 
-// Load queued slices into the idle slots of the streaming class (ascending slots; a
-// run of consecutive idle slots takes consecutive slices of one queue entry in one
-// load), with the network warm start when one is set.
+// b0 = A^H y of slices [first, first + count) (projection, inverse column and row
+// transforms, coil combine) and the initial x = z = u = 0, r = b0 with their partial sums
+int load_compute(ClassPlan& c, int first, int count, hipStream_t st) {
+    const ClassArgs& a = c.args;
+    TIMED(T2S_KERNEL_LOAD);
+    HIP_CHECK_LAUNCH(t2s::launch_project(a, first, count, st));
+    HIP_CHECK_LAUNCH(t2s::launch_passB(a, first, count, 1, 0, st));
+    HIP_CHECK_LAUNCH(t2s::launch_passC(a, first, count, 1, 0.0f, a.b0, 0, st));
+    HIP_CHECK_LAUNCH(t2s::launch_init(a, first, count, nullptr, 0, st));
+    return 0;
+}
+
+int load_range(ClassPlan& c, int first, int count, const void* sens, const void* ksp, hipMemcpyKind kind, int gfirst,
+               hipStream_t st) {
+    if (int e = load_copy(c, first, count, sens, ksp, kind, gfirst, st)) return e;
+    return load_compute(c, first, count, st);
+}
+
+// Load queued slices into the idle slots of the streaming class: each run of
+// consecutive idle slots takes the next queued slices in queue order (across queue
+// entries; one copy per slice, or one per stretch taken from one entry), then one
+// set of load launches over the run, the network warm start when one is set, and the
+// warm start's normal operator.
 int stream_refill(t2s_plan* plan, StreamState& q, ClassPlan& c, hipStream_t st) {
     const size_t N = (size_t)c.ny * c.nz;
     const size_t n = slice_images(c, plan->prm.K);
@@ -492,23 +507,30 @@ int stream_refill(t2s_plan* plan, StreamState& q, ClassPlan& c, hipStream_t st) 
             ++s;
             continue;
         }
-        while (q.head < q.items.size() && q.items[q.head].next >= q.items[q.head].count) ++q.head;
-        if (q.head == q.items.size()) break;
-        StreamItem& it = q.items[q.head];
         int r = 0;
-        while (s + r < c.S && q.slots[s + r].item < 0 && it.next + r < it.count) ++r;
-        const int j0 = it.next;
-        it.next += r;
-        if (int e = load_range(c, s, r, it.sens + (size_t)j0 * c.C * c.M * N * 8, it.ksp + (size_t)j0 * c.C * c.P * 8,
-                               hipMemcpyDeviceToDevice, it.g0 + j0, st))
-            return e;
-        q.loaded += r;
-        for (int i = 0; i < r; ++i) {
-            q.slots[s + i] = StreamSlot{(int)q.head, j0 + i, 0};
-            c.outer_run[s + i] = 0;
-            c.k_freeze[s + i] = -1;
-            c.converged[s + i] = 0;
+        while (s + r < c.S && q.slots[s + r].item < 0) {
+            while (q.head < q.items.size() && q.items[q.head].next >= q.items[q.head].count) ++q.head;
+            if (q.head == q.items.size()) break;
+            StreamItem& it = q.items[q.head];
+            // as many consecutive slices of this entry as there are idle slots in a row
+            int m = 0;
+            while (s + r + m < c.S && q.slots[s + r + m].item < 0 && it.next + m < it.count) ++m;
+            const int j0 = it.next;
+            it.next += m;
+            if (int e = load_copy(c, s + r, m, it.sens + (size_t)j0 * c.C * c.M * N * 8,
+                                  it.ksp + (size_t)j0 * c.C * c.P * 8, hipMemcpyDeviceToDevice, it.g0 + j0, st))
+                return e;
+            for (int i = 0; i < m; ++i) {
+                q.slots[s + r + i] = StreamSlot{(int)q.head, j0 + i, 0};
+                c.outer_run[s + r + i] = 0;
+                c.k_freeze[s + r + i] = -1;
+                c.converged[s + r + i] = 0;
+            }
+            r += m;
         }
+        if (r == 0) break;
+        q.loaded += r;
+        if (int e = load_compute(c, s, r, st)) return e;
         if (q.net) {
             // alpha0 = net(b0) straight into x, then r = b0 - A^H A alpha0 (t2s_set_initial)
             for (int i = 0; i < r; i += q.net_batch) {
@@ -623,6 +645,7 @@ int t2s_plan_create(const t2s_params* p, const t2s_class* classes, int n_classes
         c.S = src.nslices;
         c.gbase = gbase;
         gbase += src.nslices;
+        c.order = t2s::default_order(c.ny, c.nz, K);
         const int ny = c.ny, nz = c.nz, N = ny * nz;
         // space-time kernel, FP64, upper triangle, uncentred + transposed, / N
         std::vector<double> acc((size_t)kk2 * N, 0.0);
@@ -747,6 +770,7 @@ int t2s_profile_enable(t2s_plan* plan, int enable) {
         p.ms[k] = 0.0;
     }
     p.on = enable != 0;
+    if (plan->bound) HIP_CHECK_LAUNCH(t2s::launch_profile_mark(plan->last_stream));
     return 0;
 }
 
@@ -961,7 +985,7 @@ int t2s_set_schedule(t2s_plan* plan, int cls, int chunk, int nstreams) {
 int t2s_set_order(t2s_plan* plan, int cls, int order) {
     if (!plan) return fail(T2S_EINVAL, "plan is NULL");
     if (cls < 0 || cls >= (int)plan->cls.size()) return fail(T2S_EINVAL, "class index out of range");
-    if (order & ~(T2S_ORDER_XCD_PASS_A | T2S_ORDER_XCD_PASS_C)) return fail(T2S_EINVAL, "unknown order flags");
+    if (order & ~t2s::kOrderAll) return fail(T2S_EINVAL, "unknown schedule flags");
     plan->cls[cls].order = order;
     plan->cls[cls].args.order = order;
     return 0;
@@ -1026,8 +1050,9 @@ int t2s_autotune(t2s_plan* plan, int reps, void* stream) {
             }
         }
         // candidates: everything in one launch, or chunks of 32..2 slices over 1, 2 or 4
-        // streams, in the plain workgroup order; then the XCD-grouped orders of passes A
-        // and C with the best of those
+        // streams, with the class's default schedule flags; then every combination of
+        // the kernel schedule flags (XCD-grouped orders of passes A, C and B, pass C's
+        // one or two LDS buffers) with the best of those
         auto time_it = [&](const Sched& cand, float* ms) -> int {
             c.args.order = cand.order;
             // one warm-up, then `reps` timed CG steps (passes only, pass C writing M p to
@@ -1041,17 +1066,21 @@ int t2s_autotune(t2s_plan* plan, int reps, void* stream) {
             HIP_TRY(hipEventElapsedTime(ms, e0, e1));
             return 0;
         };
-        std::vector<Sched> cands{{0, 1, 0}};
+        const int o0 = t2s::default_order(c.ny, c.nz, plan->prm.K);
+        std::vector<Sched> cands{{0, 1, o0}};
         for (int ch : {32, 16, 8, 4, 2})
             if (ch < c.S)
-                for (int ns : {1, 2, 4}) cands.push_back({ch, ns, 0});
+                for (int ns : {1, 2, 4}) cands.push_back({ch, ns, o0});
         float best = 1e30f;
-        Sched pick{0, 1, 0};
+        Sched pick{0, 1, o0};
         for (int phase = 0; phase < 2; ++phase) {
             if (phase == 1) {
                 cands.clear();
-                for (int o : {T2S_ORDER_XCD_PASS_A, T2S_ORDER_XCD_PASS_C, T2S_ORDER_XCD_PASS_A | T2S_ORDER_XCD_PASS_C})
-                    cands.push_back({pick.chunk, pick.nstreams, o});
+                for (int o = 0; o <= t2s::kOrderAll; ++o) {
+                    // the two-buffer flag only exists where pass C has that variant
+                    if ((o & t2s::kOrderLds2C) && !t2s::passC_lds2_supported(c.nz)) continue;
+                    if (o != o0) cands.push_back({pick.chunk, pick.nstreams, o});
+                }
             }
             for (const Sched& cand : cands) {
                 float ms = 0.f;

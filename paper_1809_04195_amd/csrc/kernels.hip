@@ -159,14 +159,15 @@ template <int L>
 using RowGeom = RegGeom<L, RowPlan<L>>;
 template <int L>
 constexpr int rows_threads() { return kRowTile * RowGeom<L>::P; }
-// LDS exchange buffers of pass C: two at 384 and 512 points, where one workgroup fills
-// a CU anyway (register budget), so the waves that finished reading coil c's exchange
-// transform coil c + 1 into the other buffer without waiting for the rest: one barrier
-// per coil instead of two (pass C at 384 points: 21.8 -> 20.0 ms per 512-slice launch).
-// One buffer below, where the second would cost workgroups per CU, and in pass A,
-// which measured 2 % slower with two.
+// Pass C's LDS exchange can be double-buffered (kOrderLds2C): the waves that finished
+// reading coil c's exchange then transform coil c + 1 into the other buffer without
+// waiting for the rest, one barrier per coil instead of two.  It pays where one
+// workgroup fills a CU anyway (384 points: 21.8 -> 20.0 ms per 512-slice launch) and
+// costs workgroups per CU where the second buffer does not fit beside the others; the
+// variant exists from 256 points on and the autotuner picks per class.  (Pass A
+// measured 2 % slower with two buffers at 384 points and keeps one.)
 template <int L>
-constexpr int passC_nbuf() { return L >= 384 ? 2 : 1; }
+constexpr bool passC_lds2_ok() { return L >= 256; }
 // Occupancy targets of the row passes.  Left free, the register scheduler trades the
 // batched issue of a coil's loads for one more wave per SIMD and then waits on every
 // load in turn, which costs far more than the extra wave gains.
@@ -374,14 +375,13 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
     __shared__ float2 tw[L];
     __shared__ float2 xb[W * TB];
 
-    // A table larger than 2 MB does not stay in an XCD's L2 while the pass streams: the
-    // workgroups then go coil fastest, each XCD a contiguous run of (slice, column
-    // tile), so the C workgroups that read the same columns of the table run back to
-    // back on one XCD and share them through its L2 (the 384 x 384, K = 5 table is
-    // 9.4 MB; dealt round-robin, every coil re-read it from the Infinity Cache and the
-    // pass fetched 2.6x its algorithmic bytes)
-    constexpr int KPB = (K * (K + 1) / 2 + 3) / 4 * 16;   // table bytes per frequency
-    const Blk bk = block_coords((size_t)a.nz * L * KPB > (2u << 20));
+    // With kOrderXcdB (the default when the class's Psi table exceeds 2 MB, more than
+    // stays in an XCD's L2 while the pass streams) the workgroups go coil fastest, each
+    // XCD a contiguous run of (slice, column tile), so the C workgroups that read the
+    // same columns of the table run back to back on one XCD and share them through its
+    // L2 (the 384 x 384, K = 5 table is 9.4 MB; dealt round-robin, every coil re-read
+    // it from the Infinity Cache and the pass fetched 2.6x its algorithmic bytes)
+    const Blk bk = block_coords(a.order & kOrderXcdB);
     const int s = s0 + bk.z;
     if (!slice_active(a, s)) return;
     const int c = bk.y;
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB_inv(ClassAr
 // out = acc + rho_add p (MODE 0), out = acc (MODE 1), or the CG step (MODE 2):
 // w = acc + rho p, a = gamma / <p, M p>, x += a p, r -= a w, partial <r, r>.
 // ---------------------------------------------------------------------------
-template <int L, int MODE, int M>
+template <int L, int MODE, int M, int NBUF>
 __global__ __launch_bounds__(rows_threads<L>()) __attribute__((amdgpu_waves_per_eu(1, kPassCWavesPerSimd)))
 void k_passC(ClassArgs a, int s0, float rho_add,
                                                               float2* __restrict__ outp, int out_s0, PartialSrc gc,
@@ -563,7 +563,7 @@ void k_passC(ClassArgs a, int s0, float rho_add,
     using G = RowGeom<L>;
     constexpr int R1 = G::R1, R2 = G::R2, P = G::P, TB = G::TB, RT = kRowTile, NT = RT * P;
     static_assert(NT % 64 == 0, "block_sum needs whole waves");
-    constexpr int NBUF = passC_nbuf<L>();
+    static_assert(NBUF == 1 || (NBUF == 2 && passC_lds2_ok<L>()), "pass C LDS buffers");
     __shared__ float2 tw[L];
     __shared__ float2 xb[NBUF * RT * TB];
     __shared__ double red[16];
@@ -1062,10 +1062,10 @@ bool reg_plan(int L, int* R1, int* R2) {
     return false;
 }
 
-// LDS of the row passes (pass C's, the larger of the two)
+// LDS of the row passes (pass C's with two buffers where it has them, the largest)
 template <int L>
 static size_t rows_lds() {
-    return (L + passC_nbuf<L>() * kRowTile * RowGeom<L>::TB) * sizeof(float2) + 16 * sizeof(double);
+    return (L + (passC_lds2_ok<L>() ? 2 : 1) * kRowTile * RowGeom<L>::TB) * sizeof(float2) + 16 * sizeof(double);
 }
 template <int L>
 static size_t cols_lds() { return (L + colB<L>() * RegGeom<L>::TB) * sizeof(float2); }
@@ -1156,25 +1156,36 @@ hipError_t launch_passB(const ClassArgs& a, int s0, int count, int mode, int wan
     }
 }
 
+// pass C with one or two LDS buffers as the class's schedule flags say
+template <int L, int MODE, int M>
+static void launch_passC_t(const ClassArgs& a, dim3 grid, int s0, float rho_add, float2* out, int out_s0,
+                           PartialSrc gc, int out_buf, hipStream_t st) {
+    if constexpr (passC_lds2_ok<L>()) {
+        if (a.order & kOrderLds2C) {
+            hipLaunchKernelGGL((k_passC<L, MODE, M, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,
+                               out_s0, gc, out_buf);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_passC<L, MODE, M, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out, out_s0,
+                       gc, out_buf);
+}
+
 hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float rho_add, float2* out,
                         int out_s0, hipStream_t st) {
     const dim3 grid(a.ny / kRowTile, a.K, count);
     const PartialSrc none{nullptr, 0, 0};
     switch (a.nz) {
-#define X(L)                                                                                                  \
-    case L:                                                                                                   \
-        if (mode == 0 && a.M == 2)                                                                            \
-            hipLaunchKernelGGL((k_passC<L, 0, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,    \
-                               out_s0, none, 0);                                                              \
-        else if (mode == 0)                                                                                   \
-            hipLaunchKernelGGL((k_passC<L, 0, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,    \
-                               out_s0, none, 0);                                                              \
-        else if (a.M == 2)                                                                                    \
-            hipLaunchKernelGGL((k_passC<L, 1, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,    \
-                               out_s0, none, 0);                                                              \
-        else                                                                                                  \
-            hipLaunchKernelGGL((k_passC<L, 1, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, rho_add, out,    \
-                               out_s0, none, 0);                                                              \
+#define X(L)                                                                                 \
+    case L:                                                                                  \
+        if (mode == 0 && a.M == 2)                                                           \
+            launch_passC_t<L, 0, 2>(a, grid, s0, rho_add, out, out_s0, none, 0, st);         \
+        else if (mode == 0)                                                                  \
+            launch_passC_t<L, 0, 1>(a, grid, s0, rho_add, out, out_s0, none, 0, st);         \
+        else if (a.M == 2)                                                                   \
+            launch_passC_t<L, 1, 2>(a, grid, s0, rho_add, out, out_s0, none, 0, st);         \
+        else                                                                                 \
+            launch_passC_t<L, 1, 1>(a, grid, s0, rho_add, out, out_s0, none, 0, st);         \
         break;
         T2S_FOR_ROW_LENGTHS(X)
 #undef X
@@ -1187,14 +1198,12 @@ hipError_t launch_passC(const ClassArgs& a, int s0, int count, int mode, float r
 hipError_t launch_passC_cg(const ClassArgs& a, int s0, int count, PartialSrc gc, int out_buf, hipStream_t st) {
     const dim3 grid(a.ny / kRowTile, a.K, count);
     switch (a.nz) {
-#define X(L)                                                                                                 \
-    case L:                                                                                                  \
-        if (a.M == 2)                                                                                        \
-            hipLaunchKernelGGL((k_passC<L, 2, 2>), grid, dim3(rows_threads<L>()), 0, st, a, s0, 0.0f, nullptr, 0, \
-                               gc, out_buf);                                                                 \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_passC<L, 2, 1>), grid, dim3(rows_threads<L>()), 0, st, a, s0, 0.0f, nullptr, 0, \
-                               gc, out_buf);                                                                 \
+#define X(L)                                                                    \
+    case L:                                                                     \
+        if (a.M == 2)                                                           \
+            launch_passC_t<L, 2, 2>(a, grid, s0, 0.0f, nullptr, 0, gc, out_buf, st); \
+        else                                                                    \
+            launch_passC_t<L, 2, 1>(a, grid, s0, 0.0f, nullptr, 0, gc, out_buf, st); \
         break;
         T2S_FOR_ROW_LENGTHS(X)
 #undef X
@@ -1202,6 +1211,20 @@ hipError_t launch_passC_cg(const ClassArgs& a, int s0, int count, PartialSrc gc,
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+bool passC_lds2_supported(int nz) {
+    switch (nz) {
+#define X(L) case L: return passC_lds2_ok<L>();
+        T2S_FOR_ROW_LENGTHS(X)
+#undef X
+    }
+    return false;
+}
+
+int default_order(int ny, int nz, int K) {
+    const size_t psi_bytes = (size_t)ny * nz * ((K * (K + 1) / 2 + 3) / 4 * 16);
+    return (psi_bytes > (2u << 20) ? kOrderXcdB : 0) | (nz >= 384 ? kOrderLds2C : 0);
 }
 
 hipError_t launch_project(const ClassArgs& a, int s0, int count, hipStream_t st) {
@@ -1525,6 +1548,15 @@ hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, i
                             hipStream_t st, int gfirst) {
     hipLaunchKernelGGL(k_set_state, dim3((count + 63) / 64), dim3(64), 0, st, a, s0, count, active, frozen, kreset,
                        gfirst);
+    return hipGetLastError();
+}
+
+// empty kernel: marks where the library's event timing starts and stops in an
+// external kernel trace
+__global__ void k_profile_mark() {}
+
+hipError_t launch_profile_mark(hipStream_t st) {
+    hipLaunchKernelGGL(k_profile_mark, dim3(1), dim3(64), 0, st);
     return hipGetLastError();
 }
 

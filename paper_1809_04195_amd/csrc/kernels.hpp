@@ -28,8 +28,8 @@ struct ClassArgs {
                                  // (M runs, one per map set)
     int hist_len;                // outer-iteration capacity of the residual history
     int block;                   // LLR block edge
-    int order;                   // workgroup order of the row passes: bit 0 pass A, bit 1
-                                 // pass C grouped by XCD (kOrderXcdA / kOrderXcdC)
+    int order;                   // kernel schedule flags (kOrder*): XCD-grouped workgroup
+                                 // orders of passes A, C and B, pass C's LDS buffers
     float tau, rho;              // LLR threshold lambda / rho, ADMM penalty
     uint64_t seed;
     const float* psi;            // upper triangle of Psi, uncentred, / (ny nz), in pass-B order:
@@ -57,8 +57,17 @@ struct ClassArgs {
                                  // global slice index (the block-shift schedule's g)
 };
 
-constexpr int kOrderXcdA = 1;
-constexpr int kOrderXcdC = 2;
+constexpr int kOrderXcdA = 1;    // pass A workgroups dealt to the XCDs in runs of row tiles
+constexpr int kOrderXcdC = 2;    // the same for pass C
+constexpr int kOrderXcdB = 4;    // pass B coil-fastest, dealt in runs (coils of a column tile share Psi)
+constexpr int kOrderLds2C = 8;   // pass C double-buffers its LDS exchange (row lengths >= 256)
+constexpr int kOrderAll = 15;
+
+// schedule flags a class starts with before any tuning: pass B's coil-fastest order
+// when the class's Psi table exceeds 2 MB, pass C's two LDS buffers from 384 points
+int default_order(int ny, int nz, int K);
+// whether pass C has its two-buffer variant at this row length
+bool passC_lds2_supported(int nz);
 
 // LLR kernel flavours
 enum LlrMode { kLlrAdmm = 0, kLlrProx = 1, kLlrFista = 2 };
@@ -109,6 +118,8 @@ hipError_t launch_normalize(const ClassArgs& a, int s0, int count, float2* v, hi
 // if gfirst >= 0]) for slices [s0, s0 + count)
 hipError_t launch_set_state(const ClassArgs& a, int s0, int count, int active, int frozen, int kreset,
                             hipStream_t st, int gfirst = -1);
+// an empty kernel marking where event timing starts / stops (for external traces)
+hipError_t launch_profile_mark(hipStream_t st);
 // hist[s][counter] = sum of the LLR partials of slice s; counter += 1
 hipError_t launch_llr_finalize(const ClassArgs& a, int s0, int count, hipStream_t st);
 

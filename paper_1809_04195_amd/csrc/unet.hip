@@ -1,7 +1,8 @@
 // unet.hip -- warm-start network of the T2-Shuffling solver on gfx950: a 4-level
 // U-Net on 2K real channels (NHWC, bf16 activations, fp32 accumulation) whose
 // convolutions are implicit GEMMs on the bf16 matrix cores
-// (v_mfma_f32_16x16x16_bf16), trained with Adam on solver outputs.
+// (v_mfma_f32_16x16x32_bf16 in the convolutions, forward and data gradient;
+// v_mfma_f32_16x16x16_bf16 in the weight gradients), trained with Adam on solver outputs.
 //
 // Layer order, shapes and the packed parameter layout (per layer W[KH][KW][Cout][Cin]
 // then bias[Cout], forward order) are those of the FP64 reference used by the tests.
@@ -22,6 +23,7 @@ namespace unetk {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));   // operand type of the 32-deep MFMA
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef uint16_t bf16;
 
@@ -41,8 +43,13 @@ __host__ __device__ inline float bf2f(bf16 h) {
 
 constexpr int kNT = 256;
 
-__device__ __forceinline__ bf16x4 lo4(bf16x8 v) { return __builtin_shufflevector(v, v, 0, 1, 2, 3); }
-__device__ __forceinline__ bf16x4 hi4(bf16x8 v) { return __builtin_shufflevector(v, v, 4, 5, 6, 7); }
+// D += A B over 32 reduction indices (v_mfma_f32_16x16x32_bf16): lane l supplies
+// A[l % 16][8 (l / 16) + r] and B[8 (l / 16) + r][l % 16], r < 8 (layout checked by
+// t2s_unet_mfma_probe32)
+__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, b), c, 0,
+                                                   0, 0);
+}
 __device__ __forceinline__ void Bv8_load(bf16x8& dst, bool ok, const uint16_t* p) {
     dst = ok ? *(const bf16x8*)p : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
 }
@@ -105,10 +112,8 @@ __global__ __launch_bounds__(kNT) void k_conv(ConvArgs a) {
         }
         const bf16* wt = a.w + (size_t)tap * a.coutp * a.cinp;
         int ci0 = 0;
-        // 32 channels per step: each lane loads 8 consecutive channels (16 bytes) of A and B
-        // and feeds two MFMAs with the two halves.  The reduction index is permuted
-        // (MFMA k = 4 q + r of the first half is channel 8 q + r, of the second 8 q + 4 + r)
-        // identically for A and B, which leaves the sum unchanged
+        // 32 channels per step: each lane loads 8 consecutive channels (16 bytes) of A and B,
+        // the operands of one 32-deep MFMA
         for (; ci0 + 32 <= a.cinp; ci0 += 32) {
             const int ci = ci0 + 8 * q;
             bf16x8 A8[2], B8[2];
@@ -122,10 +127,7 @@ __global__ __launch_bounds__(kNT) void k_conv(ConvArgs a) {
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lo4(A8[i]), lo4(B8[j]), acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hi4(A8[i]), hi4(B8[j]), acc[i][j], 0, 0, 0);
-                }
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma32(A8[i], B8[j], acc[i][j]);
         }
         for (; ci0 < a.cinp; ci0 += 16) {
             const int ci = ci0 + 4 * q;
@@ -310,15 +312,27 @@ __global__ void k_bias_part(const bf16* dout, int ldo, int co_off, int C, int P,
     }
 }
 
-// grad_b[c] = sum over splits and `fold` groups of part[split][g * cout + c]
-__global__ void k_bias_reduce(const float* part, int nsplit, int C, int fold, float* grad) {
+// grad_b[c] = sum over splits and `fold` groups of part[split][g * cout + c]: 16
+// channels per workgroup, 16 lanes per channel each summing every 16th split (FP64),
+// the lane sums combined in a fixed order (deterministic)
+constexpr int kBiasCh = 16, kBiasLanes = 16;
+__global__ __launch_bounds__(kBiasCh * kBiasLanes) void k_bias_reduce(const float* part, int nsplit, int C, int fold,
+                                                                       float* grad) {
+    __shared__ double red[kBiasLanes][kBiasCh];
     const int cout = C / fold;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cout) return;
+    const int ch = threadIdx.x % kBiasCh, lane = threadIdx.x / kBiasCh;
+    const int c = blockIdx.x * kBiasCh + ch;
     double s = 0.0;
-    for (int k = 0; k < nsplit; ++k)
-        for (int g = 0; g < fold; ++g) s += part[(size_t)k * C + g * cout + c];
-    grad[c] = (float)s;
+    if (c < cout)
+        for (int k = lane; k < nsplit; k += kBiasLanes)
+            for (int g = 0; g < fold; ++g) s += part[(size_t)k * C + g * cout + c];
+    red[lane][ch] = s;
+    __syncthreads();
+    if (lane == 0 && c < cout) {
+        double t = 0.0;
+        for (int l = 0; l < kBiasLanes; ++l) t += red[l][ch];
+        grad[c] = (float)t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -389,12 +403,23 @@ __global__ void k_unshuffle(const bf16* dup, int ld, int off, int C, int B, int 
 }
 
 // per-slice scale s = max |b0| (FP64 reduction per slice, one workgroup per slice)
+// scale[s] = max |b0| over slice s (0 for an all-zero slice): k_zero_scale, then
+// kScaleBlocks workgroups per slice fold their maxima in with an integer atomic max
+// (non-negative floats order like their bit patterns)
+constexpr int kScaleBlocks = 64;
+__global__ void k_zero_scale(float* scale, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) scale[i] = 0.f;
+}
+
 __global__ void k_slice_scale(const float2* b0, int K, int N, float* scale) {
     __shared__ float red[kNT];
-    const int s = blockIdx.x;
+    const int s = blockIdx.y;
+    const size_t n = (size_t)K * N;
+    const float2* v0 = b0 + (size_t)s * n;
     float m = 0.f;
-    for (size_t i = threadIdx.x; i < (size_t)K * N; i += kNT) {
-        const float2 v = b0[(size_t)s * K * N + i];
+    for (size_t i = (size_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (size_t)kScaleBlocks * kNT) {
+        const float2 v = v0[i];
         m = fmaxf(m, sqrtf(v.x * v.x + v.y * v.y));
     }
     red[threadIdx.x] = m;
@@ -403,7 +428,7 @@ __global__ void k_slice_scale(const float2* b0, int K, int N, float* scale) {
         if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) scale[s] = red[0];   // 0 for an all-zero slice
+    if (threadIdx.x == 0) atomicMax((unsigned int*)scale + s, __float_as_uint(red[0]));
 }
 
 // complex [S][K][H][W] / scale[s] -> fp32 [S][H][W][2K] and bf16 [S][H][W][ldb] (zero padded)
@@ -511,6 +536,18 @@ __global__ void k_mfma_probe(const bf16* A, const bf16* B, float* D) {
         b[r] = (short)B[(4 * (l / 16) + r) * 16 + l % 16];
     }
     floatx4 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) D[(4 * (l / 16) + r) * 16 + l % 16] = d[r];
+}
+
+// the same for the 32-deep product: D = A B, A 16 x 32, B 32 x 16
+__global__ void k_mfma_probe32(const bf16* A, const bf16* B, float* D) {
+    const int l = threadIdx.x;
+    bf16x8 a, b;
+    for (int r = 0; r < 8; ++r) {
+        a[r] = (short)A[(l % 16) * 32 + 8 * (l / 16) + r];
+        b[r] = (short)B[(8 * (l / 16) + r) * 16 + l % 16];
+    }
+    const floatx4 d = mfma32(a, b, floatx4{0.f, 0.f, 0.f, 0.f});
     for (int r = 0; r < 4; ++r) D[(4 * (l / 16) + r) * 16 + l % 16] = d[r];
 }
 
@@ -675,8 +712,9 @@ int wgrad(t2s_unet* u, const Layer& Ly, const bf16* dout, int ldo, int co_off, c
     hipLaunchKernelGGL(unetk::k_bias_part, dim3(bsplit), dim3(256), 0, st, dout, ldo, co_off, C, P, bpps,
                        at<float>(u, u->o_bpart));
     ULAUNCH();
-    hipLaunchKernelGGL(unetk::k_bias_reduce, dim3((C / bias_fold + 255) / 256), dim3(256), 0, st,
-                       at<float>(u, u->o_bpart), bsplit, C, bias_fold, at<float>(u, u->o_g + Ly.boff * 4));
+    hipLaunchKernelGGL(unetk::k_bias_reduce, dim3((C / bias_fold + unetk::kBiasCh - 1) / unetk::kBiasCh),
+                       dim3(unetk::kBiasCh * unetk::kBiasLanes), 0, st, at<float>(u, u->o_bpart), bsplit, C, bias_fold,
+                       at<float>(u, u->o_g + Ly.boff * 4));
     ULAUNCH();
     return 0;
 }
@@ -1092,8 +1130,9 @@ int t2s_unet_forward(t2s_unet* u, const void* b0, void* alpha0, int B, void* str
     if (B < 1 || B > u->maxB) return ufail(T2S_EINVAL, "batch out of range");
     hipStream_t st = (hipStream_t)stream;
     const int HW = u->H * u->W;
-    hipLaunchKernelGGL(unetk::k_slice_scale, dim3(B), dim3(unetk::kNT), 0, st, (const float2*)b0, u->K, HW,
-                       at<float>(u, u->o_scale));
+    hipLaunchKernelGGL(unetk::k_zero_scale, dim3((B + 63) / 64), dim3(64), 0, st, at<float>(u, u->o_scale), B);
+    hipLaunchKernelGGL(unetk::k_slice_scale, dim3(unetk::kScaleBlocks, B), dim3(unetk::kNT), 0, st, (const float2*)b0,
+                       u->K, HW, at<float>(u, u->o_scale));
     ULAUNCH();
     if (int e = pack_complex(u, b0, B, at<float>(u, u->o_x32), at<bf16>(u, u->o_xb), st)) return e;
     if (int e = forward(u, B, st)) return e;
@@ -1111,8 +1150,9 @@ int t2s_unet_train_step(t2s_unet* u, const void* b0, const void* target, int B, 
     if (!(lr > 0) || !std::isfinite(lr)) return ufail(T2S_EINVAL, "learning rate must be > 0");
     hipStream_t st = (hipStream_t)stream;
     const int HW = u->H * u->W;
-    hipLaunchKernelGGL(unetk::k_slice_scale, dim3(B), dim3(unetk::kNT), 0, st, (const float2*)b0, u->K, HW,
-                       at<float>(u, u->o_scale));
+    hipLaunchKernelGGL(unetk::k_zero_scale, dim3((B + 63) / 64), dim3(64), 0, st, at<float>(u, u->o_scale), B);
+    hipLaunchKernelGGL(unetk::k_slice_scale, dim3(unetk::kScaleBlocks, B), dim3(unetk::kNT), 0, st, (const float2*)b0,
+                       u->K, HW, at<float>(u, u->o_scale));
     ULAUNCH();
     if (int e = pack_complex(u, b0, B, at<float>(u, u->o_x32), at<bf16>(u, u->o_xb), st)) return e;
     if (int e = pack_complex(u, target, B, at<float>(u, u->o_t32), nullptr, st)) return e;
@@ -1204,6 +1244,28 @@ int t2s_unet_mfma_probe_static(const float* A, const float* B, float* D, int cou
     hipLaunchKernelGGL(unetk::k_mfma_probe, dim3(count), dim3(64), 0, 0, (const bf16*)da, (const bf16*)db, dd);
     ULAUNCH();
     UHIP(hipMemcpy(D, dd, (size_t)count * 1024, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+int t2s_unet_mfma_probe32(const float* A, const float* B, float* D) {
+    if (!A || !B || !D) return ufail(T2S_EINVAL, "NULL argument");
+    std::vector<bf16> a(512), b(512);
+    for (int i = 0; i < 512; ++i) {
+        a[i] = unetk::f2bf(A[i]);
+        b[i] = unetk::f2bf(B[i]);
+    }
+    void *da = nullptr, *db = nullptr, *dd = nullptr;
+    UHIP(hipMalloc(&da, 1024));
+    UHIP(hipMalloc(&db, 1024));
+    UHIP(hipMalloc(&dd, 1024));
+    UHIP(hipMemcpy(da, a.data(), 1024, hipMemcpyHostToDevice));
+    UHIP(hipMemcpy(db, b.data(), 1024, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(unetk::k_mfma_probe32, dim3(1), dim3(64), 0, 0, (const bf16*)da, (const bf16*)db, (float*)dd);
+    ULAUNCH();
+    UHIP(hipMemcpy(D, dd, 1024, hipMemcpyDeviceToHost));
+    (void)hipFree(da);
+    (void)hipFree(db);
+    (void)hipFree(dd);
     return 0;
 }
 

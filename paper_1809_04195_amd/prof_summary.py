@@ -1,16 +1,18 @@
 """Summaries of rocprofv3 output for the kernels of this library.
 
     # HBM bytes per launch from two counter runs of the same command (FETCH_SIZE, then
-    # WRITE_SIZE), calibrated on the 1 GiB device copy that `bench.py --copy-probe` makes
+    # WRITE_SIZE), calibrated on the 1 GiB device copy that `bench.py --copy-probe` makes,
+    # optionally over the launches of the n-th interval the library timed
     python -m paper_1809_04195_amd.prof_summary traffic --fetch DIR --write DIR \\
-        --workload vol320_256x256_c8_t80_k4 --schedule 0,1 --out profiles/hbm_traffic_<workload>.json
+        --workload vol320_256x256_c8_t80_k4 --schedule 0,1 [--window 1] --out profiles/hbm_traffic_<workload>.json
 
     # per-kernel-family averages and utilisation metrics of one or more counter runs
     python -m paper_1809_04195_amd.prof_summary counters DIR [DIR ...]
 
     # markdown table of a --kernel-trace --stats run (csv or rocpd database output),
-    # optionally from the N-th dispatch of a named kernel on (the timed region)
-    python -m paper_1809_04195_amd.prof_summary stats DIR [--after k_project:2]
+    # optionally from the N-th dispatch of a named kernel on, or only the launches of the
+    # n-th interval the library timed (t2s_profile_enable on .. off)
+    python -m paper_1809_04195_amd.prof_summary stats DIR [--after k_project:2] [--window 1]
 
 DIR is a rocprofv3 output directory (or the CSV file itself).  Utilisation metrics
 follow rocprofv3's own derived-metric definitions on MI355X (256 CUs, 1024 SIMDs,
@@ -88,11 +90,27 @@ def copy_probe(fetch_path, write_path):
     return fd[i], wd[i]
 
 
-def read_counters(path):
-    """{family: {"n": dispatches, "dur_ns": mean duration, counter: mean value}}"""
+def _window_ids(rows, window):
+    """Dispatch-id range of the n-th interval between k_profile_mark dispatches (all when
+    window is 0)."""
+    if not window:
+        return 0, 1 << 62
+    marks = sorted({int(r["Dispatch_Id"]) for r in rows if "k_profile_mark" in r["Kernel_Name"]})
+    if len(marks) < 2 * window:
+        raise ValueError(f"fewer than {2 * window} profile marks")
+    return marks[2 * window - 2], marks[2 * window - 1]
+
+
+def read_counters(path, window=0):
+    """{family: {"n": dispatches, "dur_ns": mean duration, counter: mean value}}, over the
+    dispatches of the n-th timed interval when window = n > 0."""
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
     disp = collections.defaultdict(dict)
-    for r in csv.DictReader(open(_csv(path, "counter_collection.csv"))):
+    rows = list(csv.DictReader(open(_csv(path, "counter_collection.csv"))))
+    lo, hi = _window_ids(rows, window)
+    for r in rows:
+        if not lo < int(r["Dispatch_Id"]) < hi:
+            continue
         f = family(r["Kernel_Name"])
         vals[f][r["Counter_Name"]].append(float(r["Counter_Value"]))
         disp[f][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), r["Kernel_Name"])
@@ -108,22 +126,34 @@ def read_counters(path):
 
 
 def traffic(args):
-    fe = read_counters(args.fetch)
-    wr = read_counters(args.write)
+    fe = read_counters(args.fetch, args.window)
+    wr = read_counters(args.write, args.window)
     fcopy, wcopy = copy_probe(args.fetch, args.write)
     fscale = COPY_PROBE_BYTES / (fcopy * 1024.0)
     wscale = COPY_PROBE_BYTES / (wcopy * 1024.0)
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
     res = {"kernels_source_sha256_16": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16],
-           "workload": args.workload, "schedule": args.schedule, "order": args.order, "fetch_scale": fscale,
+           "workload": args.workload, "schedule": args.schedule, "order": args.order, "window": args.window,
+           "fetch_scale": fscale,
            "write_scale": wscale,
            "copy_probe_bytes": COPY_PROBE_BYTES, "traffic": {}}
+    alg = {}
+    if args.bench:
+        # algorithmic bytes per launch of the same run (the bench line it printed; FILE:KEY
+        # takes the kernel table of entry KEY, e.g. vol320_fixed)
+        path, _, key = args.bench.partition(":")
+        line = json.loads([x for x in open(path).read().splitlines() if x.startswith("{")][-1])
+        alg = {k: v.get("alg_bytes_per_launch") for k, v in (line[key] if key else line)["kernels"].items()}
     for fam in ("pass_a", "pass_b", "pass_c", "llr_admm"):
         if fam in fe and fam in wr:
             rb = fe[fam]["FETCH_SIZE"] * 1024.0 * fscale
             wb = wr[fam]["WRITE_SIZE"] * 1024.0 * wscale
-            res["traffic"][fam] = {"bytes_per_launch": rb + wb, "read_bytes": rb, "write_bytes": wb,
-                                   "launches": fe[fam]["n"], "avg_ms": fe[fam]["dur_ns"] / 1e6}
+            e = {"bytes_per_launch": rb + wb, "read_bytes": rb, "write_bytes": wb, "launches": fe[fam]["n"],
+                 "avg_ms": fe[fam]["dur_ns"] / 1e6}
+            if alg.get(fam):
+                e["alg_bytes_per_launch"] = alg[fam]
+                e["ratio_to_alg"] = (rb + wb) / alg[fam]
+            res["traffic"][fam] = e
     txt = json.dumps(res, indent=1)
     if args.out:
         open(args.out, "w").write(txt + "\n")
@@ -177,21 +207,22 @@ def counters(args):
         print(f"| {f} | {n} | {us:.1f} | " + " | ".join(f"{m[k]:.2f}" if k in m else "" for k in keys) + " |")
 
 
-def _stats_rows(path, after=""):
+def _stats_rows(path, after="", window=0):
     """[(name, calls, total ns, average ns, percent)] of a --kernel-trace --stats run:
     its kernel_stats.csv (csv output) or its rocpd database (the default output).
     after = "NAME:N" keeps the dispatches from the N-th dispatch of a kernel whose name
-    contains NAME on (database output only): the timed region of a run."""
+    contains NAME on; window = n keeps those of the n-th timed interval of the library
+    (between the n-th pair of k_profile_mark dispatches); database output only."""
     dbs = sorted(glob.glob(os.path.join(path, "**", "*.db"), recursive=True)) if os.path.isdir(path) else (
         [path] if path.endswith(".db") else [])
     if not dbs:
-        if after:
-            raise ValueError("--after needs the rocpd database output")
+        if after or window:
+            raise ValueError("--after / --window need the rocpd database output")
         return [(r["Name"], int(r["Calls"]), int(r["TotalDurationNs"]), float(r["AverageNs"]),
                  float(r["Percentage"])) for r in csv.DictReader(open(_csv(path, "kernel_stats.csv")))]
     import sqlite3
     db = sqlite3.connect(dbs[0])
-    t0 = 0
+    t0, t1 = 0, 1 << 62
     if after:
         key, n = after.rsplit(":", 1)
         starts = [r[0] for r in db.execute("select start from kernels where instr(name, ?) > 0 order by start",
@@ -199,8 +230,16 @@ def _stats_rows(path, after=""):
         if len(starts) < int(n):
             raise ValueError(f"fewer than {n} dispatches of {key}")
         t0 = starts[int(n) - 1]
-    rows = list(db.execute("select name, count(*), sum(end - start) from kernels where start >= ? group by name "
-                           "order by sum(end - start) desc", (t0,)))
+    if window:
+        # the n-th interval between an enabling and a disabling call of t2s_profile_enable
+        marks = [r[0] for r in db.execute("select start from kernels where instr(name, 'k_profile_mark') > 0 "
+                                          "order by start")]
+        if len(marks) < 2 * window:
+            raise ValueError(f"fewer than {2 * window} profile marks")
+        t0, t1 = marks[2 * window - 2], marks[2 * window - 1]
+    rows = list(db.execute("select name, count(*), sum(end - start) from kernels where start >= ? and start <= ? "
+                           "and instr(name, 'k_profile_mark') = 0 group by name order by sum(end - start) desc",
+                           (t0, t1)))
     tot = sum(r[2] for r in rows) or 1
     return [(n, c, t, t / c, 100.0 * t / tot) for n, c, t in rows]
 
@@ -208,7 +247,7 @@ def _stats_rows(path, after=""):
 def stats(args):
     print("| kernel | calls | total (ns) | average (ns) | % |")
     print("|---|---|---|---|---|")
-    for name, calls, total, avg, pct in _stats_rows(args.dir, args.after):
+    for name, calls, total, avg, pct in _stats_rows(args.dir, args.after, args.window):
         print(f"| `{name[:90]}` | {calls} | {total} | {avg:.0f} | {pct:.2f} |")
 
 
@@ -221,12 +260,18 @@ def main():
     t.add_argument("--workload", required=True)
     t.add_argument("--schedule", default="0,1")
     t.add_argument("--order", type=int, default=0)
+    t.add_argument("--window", type=int, default=0,
+                   help="n > 0: only the dispatches of the n-th interval the library timed")
+    t.add_argument("--bench", default="",
+                   help="bench.py output of the same run, FILE or FILE:KEY (algorithmic bytes per launch)")
     t.add_argument("--out", default="")
     c = sub.add_parser("counters")
     c.add_argument("dirs", nargs="+")
     s = sub.add_parser("stats")
     s.add_argument("dir")
     s.add_argument("--after", default="", help="NAME:N: from the N-th dispatch of a kernel named *NAME* on")
+    s.add_argument("--window", type=int, default=0,
+                   help="n: the launches of the n-th interval the library timed (t2s_profile_enable on .. off)")
     args = ap.parse_args()
     {"traffic": traffic, "counters": counters, "stats": stats}[args.cmd](args)
 

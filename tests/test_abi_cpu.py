@@ -194,14 +194,32 @@ def test_schedule_and_order_validation():
     code, h = _create(phi, cls)
     assert code == 0
     L = T.lib()
-    assert L.t2s_set_order(h, 0, 4) == T.T2S_EINVAL
+    assert T.t2s_get_order(h, 0) == 0      # 32 x 48: small Psi table, one LDS buffer
+    assert L.t2s_set_order(h, 0, 16) == T.T2S_EINVAL
     assert L.t2s_set_order(h, 1, 0) == T.T2S_EINVAL
     assert L.t2s_set_order(h, 0, T.T2S_ORDER_XCD_PASS_A | T.T2S_ORDER_XCD_PASS_C) == 0
     assert T.t2s_get_order(h, 0) == 3
+    assert L.t2s_set_order(h, 0, T.T2S_ORDER_XCD_PASS_B | T.T2S_ORDER_PASS_C_LDS2) == 0
+    assert T.t2s_get_order(h, 0) == 12
     assert L.t2s_set_schedule(h, 0, -1, 1) == T.T2S_EINVAL
     assert L.t2s_set_schedule(h, 0, 2, 9) == T.T2S_EINVAL
     assert L.t2s_set_schedule(h, 0, 2, 3) == 0
     assert T.t2s_get_schedule(h, 0) == (2, 3)
+    T.t2s_plan_destroy(h)
+
+
+@pytest.mark.parametrize("ny,nz,K,expected", [
+    (384, 384, 5, 12),    # 9.4 MB Psi table: pass B coil-fastest; 384 points: two LDS buffers
+    (256, 256, 4, 4),     # 3.1 MB table; one LDS buffer
+    (64, 64, 3, 0),
+])
+def test_default_schedule_flags(ny, nz, K, expected):
+    phi = _phi(T_=6, K=K)
+    masks = np.zeros((6, ny, nz), np.uint8)
+    masks[:, 0, 0] = 1
+    code, h = _create(phi, [(ny, nz, 2, 1, masks)])
+    assert code == 0
+    assert T.t2s_get_order(h, 0) == expected
     T.t2s_plan_destroy(h)
 
 

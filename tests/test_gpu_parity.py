@@ -355,6 +355,23 @@ def test_workgroup_orders_bitwise():
         assert np.array_equal(outs[order], outs[0]), order
 
 
+def test_every_kernel_schedule_flag_combination_bitwise():
+    _say("all 16 kernel schedule flag combinations (XCD orders of passes A/C/B, pass C's LDS buffers) at 32 x 256")
+    phi, sens, masks, ksp = random_problem(36, 32, 256, 3, 8, 3, S=4, frac=0.3)
+    outs = []
+    for order in range(16):
+        plan = _plan(phi, [dict(ny=32, nz=256, ncoils=3, nslices=4, masks=masks)], lam=0.05, rho=0.1, n_outer=3,
+                     n_cg=3, seed=18)
+        T.t2s_set_order(plan.handle, 0, order)
+        plan.load(0, 0, sens, ksp)
+        plan.reconstruct(T.T2S_BATCHED_GRAPH if order % 2 else T.T2S_BATCHED)
+        outs.append(plan.read(0, 0, 4))
+        plan.close()
+    assert np.abs(outs[0]).max() > 0
+    for order in range(1, 16):
+        assert np.array_equal(outs[order], outs[0]), order
+
+
 def test_slice_offset_splits_volume_bitwise():
     _say("a 4-slice plan vs two 2-slice plans with global slice offsets 0 and 2")
     phi, sens, masks, ksp = random_problem(35, 64, 64, 3, 8, 3, S=4, frac=0.3)

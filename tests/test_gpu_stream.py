@@ -6,7 +6,8 @@ slice the result and the stop / freeze decisions of a batch solve of the same sl
 * 13 slices of 64 x 64 (C=4, T=16, K=3, random 2D phantoms at SNR ~ U[15, 40], one
   mask set at 4 % per echo), tolerance 1e-3, through 4 slots, against one 13-slice
   batch: coefficients bitwise equal, reports equal; run in steps of at least 3
-  completed slices; the same slices submitted a second time give the same results;
+  completed slices; the same slices submitted a second time, and a third time as one
+  queue entry per slice in reverse order, give the same results;
 * the same with a network warm start (3-level network with random weights) against
   set_initial(net(b0)) + reconstruct;
 * the held-out 320-slice 256^2 volume (C=8, T=80, K=4) to tolerance 1e-4, cold,
@@ -89,9 +90,12 @@ def test_stream_matches_batch_cold(small):
     ds, dk = torch.from_numpy(sens).cuda(), torch.from_numpy(ksp).cuda()
     out1 = torch.zeros((NS, K, NY, NZ), dtype=torch.complex64, device="cuda")
     out2 = torch.zeros_like(out1)
+    out3 = torch.zeros_like(out1)
     plan.stream_open(None, T.T2S_BATCHED_GRAPH)
     rep1 = plan.stream_submit(ds, dk, out1, 0)
     rep2 = plan.stream_submit(ds, dk, out2, 0)      # the same slices again
+    # and once more, one queue entry per slice in reverse order (refills across entries)
+    rep3 = [plan.stream_submit(ds[g:g + 1], dk[g:g + 1], out3[g:g + 1], g) for g in reversed(range(NS))]
     steps, prev, code = 0, 0, 0
     while True:
         c, st = plan.stream_run(3)
@@ -101,17 +105,18 @@ def test_stream_matches_batch_cold(small):
         prev = done
         if inflight == 0:
             break
-    assert st["loaded"] == 2 * NS
-    assert st["slice_outer"] == 2 * sum(its)
+    assert st["loaded"] == 3 * NS
+    assert st["slice_outer"] == 3 * sum(its)
     torch.cuda.synchronize()
     _say(f"stream through {SLOTS} slots: {done} slices in {steps} calls")
-    assert done == 2 * NS and code == code_b
-    for out, rep in ((out1, rep1), (out2, rep2)):
+    assert done == 3 * NS and code == code_b
+    rep3 = [T.Plan.stream_reports(r)[0] for r in reversed(rep3)]
+    for out, rep in ((out1, T.Plan.stream_reports(rep1)), (out2, T.Plan.stream_reports(rep2)), (out3, rep3)):
         got = out.cpu().numpy()
         d = float(np.abs(got - alpha_b).max())
         _say(f"  max |alpha_stream - alpha_batch| = {d:.3e} (rel L2 {rel(got, alpha_b):.2e})")
         assert d == 0.0
-        _same_reports(T.Plan.stream_reports(rep), rep_b)
+        _same_reports(rep, rep_b)
     plan.stream_close()
     plan.close()
 

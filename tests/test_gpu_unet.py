@@ -40,6 +40,15 @@ def test_mfma_lane_layout():
     assert np.array_equal(D, (A.astype(np.float64) @ B).astype(np.float32))
 
 
+def test_mfma32_lane_layout():
+    """The 32-deep product the convolution kernels use: exact on small dyadic values."""
+    rng = np.random.default_rng(1)
+    A = rng.integers(-8, 9, (16, 32)).astype(np.float32) / 8
+    B = rng.integers(-8, 9, (32, 16)).astype(np.float32) / 4
+    D = T.t2s_unet_mfma_probe32(A, B)
+    assert np.array_equal(D, (A.astype(np.float64) @ B).astype(np.float32))
+
+
 def _tiny(seed, K=2, base=16, levels=3, H=16, W=16, B=2):
     rng = np.random.default_rng(seed)
     params = U.init_params(2 * K, base, levels, seed=seed, final_scale=1.0)
