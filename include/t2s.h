@@ -240,7 +240,12 @@ int t2s_read_coeffs(t2s_plan* plan, int cls, int first, int count, void* out, in
                     int mem, void* stream);
 
 /* Per-slice report of the last reconstruct (synchronous host call; call after the
- * stream has finished the reconstruct). */
+ * stream has finished the reconstruct): outer iterations, frozen shift, convergence
+ * and the final residuals.  The time per phase of the solve (passes A / B / C, LLR
+ * z-step, load) comes from the plan's event timing: t2s_profile_enable before the
+ * solve, t2s_profile_read after it (launches and summed milliseconds per kernel
+ * family; with all slices of a class per launch the phases are shared by the slices,
+ * so the timing is per plan, not per slice). */
 int t2s_get_slice_report(const t2s_plan* plan, int cls, int slice, t2s_slice_report* out);
 
 /* ---- Operator entry points (same kernels as the solver; used for verification) ---- */

@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libt2s.so")
+# T2S_LIB points at another build of the same library (the sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("T2S_LIB") or os.path.join(HERE, "libt2s.so")
 
 T2S_OK = 0
 T2S_WNOTCONVERGED = 1

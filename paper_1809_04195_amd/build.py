@@ -52,6 +52,26 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+def build_sanitized(verbose: bool = True) -> str:
+    """A copy of the library whose host code in api.cpp (plan tables, validation, the
+    ADMM / stream schedulers) is built with AddressSanitizer and UBSan, linked with the
+    objects of the last build(): ``_build/libt2s_asan.so``.  Load it with the clang ASan
+    runtime preloaded (the CPU tests do).  Device code is unaffected."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build")
+    objs = [os.path.join(objdir, "kernels.hip.o"), os.path.join(objdir, "unet.hip.o")]
+    for o in objs:
+        if not os.path.exists(o):
+            raise FileNotFoundError(f"{o} is missing: run build() first")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+    api = os.path.join(objdir, "api.asan.o")
+    _run([hipcc, f"--offload-arch={ARCH}", "-O1", "-g", "-std=c++17", "-fPIC", "-Wall", "-fno-omit-frame-pointer",
+          *san, "-c", os.path.join(CSRC, "api.cpp"), "-o", api])
+    out = os.path.join(objdir, "libt2s_asan.so")
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libasan", *san, "-o", out, *objs, api])
+    return out
+
+
 if __name__ == "__main__":
     build()
     sys.exit(0)
