@@ -277,6 +277,35 @@ def test_tolerance_mode_replay_parity():
                  check_every=5)
     _say(f"  oracle's own decisions: k_freeze {own.k_freeze} outer {own.n_outer}")
     plan.close()
+    # the GPU's stop rule takes the oracle's decisions (within one decision interval)
+    assert abs(own.k_freeze - rep["k_freeze"]) <= 5 and abs(own.n_outer - rep["outer_iterations"]) <= 5, (own, rep)
+
+
+def test_tolerance_mode_on_a_side_stream_with_device_inputs():
+    import torch
+    _say("tolerance mode on a non-blocking torch stream, device inputs, vs the default stream")
+    cfg, phi, cl = _cfg0()
+    kw = dict(lam=cfg["lam"], rho=cfg["rho"], n_outer=300, n_cg=5, seed=cfg["seed"], tol=1e-4, freeze_window=5,
+              freeze_stall=0.05, check_every=5)
+    classes = [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=1, masks=cl.masks)]
+    ref_plan = _plan(phi, classes, **kw)
+    ref_plan.load(0, 0, cl.sens, cl.ksp)
+    ref_plan.reconstruct(T.T2S_BATCHED_GRAPH)
+    ref, ref_rep = ref_plan.read(0, 0, 1), ref_plan.report(0, 0)
+    ref_plan.close()
+    plan = _plan(phi, classes, **kw)
+    side = torch.cuda.Stream()
+    ds, dk = torch.from_numpy(cl.sens).cuda(), torch.from_numpy(cl.ksp).cuda()
+    side.wait_stream(torch.cuda.current_stream())
+    T.t2s_load_slices(plan.handle, 0, 0, 1, ds, dk, side)
+    T.t2s_reconstruct(plan.handle, T.T2S_BATCHED_GRAPH, side)
+    side.synchronize()
+    got, rep = plan.read(0, 0, 1, stream=side), plan.report(0, 0)
+    plan.close()
+    _say(f"  side stream: outer {rep['outer_iterations']} freeze {rep['k_freeze']}; default: "
+         f"{ref_rep['outer_iterations']} {ref_rep['k_freeze']}")
+    assert (rep["outer_iterations"], rep["k_freeze"]) == (ref_rep["outer_iterations"], ref_rep["k_freeze"])
+    assert np.array_equal(got, ref)
 
 
 def test_tolerance_mode_empty_slice_stops_first_check():
