@@ -14,16 +14,16 @@ prescribes and stores, in ``tests/golden/oracle_<case>.npz``:
 
 Cases (the GPU tests run the whole plan and compare these slices):
 
-  cfg1_s{0,160,250}    320-slice 256^2 C8 T80 K4 volume, 100 outer x 5 CG
-  cfg2_c{0,1,2}        mixed 48-slice batch, one slice per shape class, 100 x 5
-  cfg3_s{120,200}      held-out 320-slice 256^2 volume, cold start, tolerance 1e-4
-  cfg4_s{200,330}      512-slice 384^2 C16 T100 K5 volume, cold start, tolerance 1e-4
+  vol320_s{0,160,250}    320-slice 256^2 C8 T80 K4 volume, 100 outer x 5 CG
+  mixed48_c{0,1,2}       mixed 48-slice batch, one slice per shape class, 100 x 5
+  eval320_s{120,200}     held-out 320-slice 256^2 volume, cold start, tolerance 1e-4
+  vol512_s{200,330}      512-slice 384^2 C16 T100 K5 volume, cold start, tolerance 1e-4
 
 The tolerance cases take 0.5-1.5 h of one core each (the 384^2 ones); the
 script runs the cases in parallel worker processes and skips cases whose file
 already exists, so it can be resumed.
 
-    python tests/golden/make_oracle_fixtures.py [--jobs 8] [--only cfg4_s200,...]
+    python tests/golden/make_oracle_fixtures.py [--jobs 8] [--only vol512_s200,...]
 """
 
 from __future__ import annotations
@@ -39,16 +39,16 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 
 # (case name, workload, shape class, slice index inside the class)
 CASES = [
-    ("cfg4_s200", 4, 0, 200),
-    ("cfg4_s330", 4, 0, 330),
-    ("cfg3_s120", 3, 0, 120),
-    ("cfg3_s200", 3, 0, 200),
-    ("cfg1_s0", 1, 0, 0),
-    ("cfg1_s160", 1, 0, 160),
-    ("cfg1_s250", 1, 0, 250),
-    ("cfg2_c0", 2, 0, 0),
-    ("cfg2_c1", 2, 1, 8),
-    ("cfg2_c2", 2, 2, 15),
+    ("vol512_s200", 4, 0, 200),
+    ("vol512_s330", 4, 0, 330),
+    ("eval320_s120", 3, 0, 120),
+    ("eval320_s200", 3, 0, 200),
+    ("vol320_s0", 1, 0, 0),
+    ("vol320_s160", 1, 0, 160),
+    ("vol320_s250", 1, 0, 250),
+    ("mixed48_c0", 2, 0, 0),
+    ("mixed48_c1", 2, 1, 8),
+    ("mixed48_c2", 2, 2, 15),
 ]
 
 # Tolerance-mode decision constants of the workloads (freeze window, stall fraction,

@@ -86,7 +86,7 @@ def test_vol320_full_schedule_and_cg_residual_drift():
     plan.reconstruct(T.T2S_BATCHED_GRAPH)
     torch.cuda.synchronize()
     for s in (0, 160, 250):
-        _compare(f"slice {s}", plan.read(0, s, 1)[0], _fixture(f"cfg1_s{s}"))
+        _compare(f"slice {s}", plan.read(0, s, 1)[0], _fixture(f"vol320_s{s}"))
     # CG residual tracked over 100 x 5 steps vs recomputed: r = b0 + rho (z - u) - (A^H A + rho) alpha
     s = 160
     al = plan.read(0, s, 1, T.T2S_ALPHA, device=True)
@@ -121,7 +121,7 @@ def test_mixed48_full_schedule_graph_autotuned():
         plan.load(ci, 0, c.sens, c.ksp)
     plan.reconstruct(T.T2S_BATCHED_GRAPH)
     for ci, c in enumerate(cls):
-        fx = _fixture(f"cfg2_c{ci}")
+        fx = _fixture(f"mixed48_c{ci}")
         assert int(fx["cls"]) == ci
         s = int(fx["slice"])
         _say(f"  class {ci} ({c.ny}x{c.nz} C{c.ncoils}): schedule {T.t2s_get_schedule(plan.handle, ci)}")
@@ -151,7 +151,7 @@ def test_eval320_tolerance_mode():
     code = plan.reconstruct(T.T2S_BATCHED_GRAPH)
     assert code == 0
     for s in (120, 200):
-        _check_tolerance_slice(plan, s, _fixture(f"cfg3_s{s}"), f"slice {s}")
+        _check_tolerance_slice(plan, s, _fixture(f"eval320_s{s}"), f"slice {s}")
     plan.close()
     del plan
     _free()
@@ -192,7 +192,7 @@ def test_vol512_384x384_c16_k5_tolerance_mode():
     _say(f"  solved in {time.perf_counter() - t1:.1f} s")
     assert code == 0
     for s in readout:
-        _check_tolerance_slice(plan, s, _fixture(f"cfg4_s{s}"), f"plan slice {s}")
+        _check_tolerance_slice(plan, s, _fixture(f"vol512_s{s}"), f"plan slice {s}")
     empty = plan.read(0, 1, 1)[0]
     rep = plan.report(0, 1)
     plan.close()

@@ -180,7 +180,7 @@ def test_eval320_streamed_through_64_slots_against_oracle():
     reps = T.Plan.stream_reports(rep)
     assert all(r["converged"] == 1 for r in reps)
     for s in (120, 200):
-        with np.load(os.path.join(GOLDEN, f"oracle_cfg3_s{s}.npz")) as f:
+        with np.load(os.path.join(GOLDEN, f"oracle_eval320_s{s}.npz")) as f:
             fx = {k: f[k] for k in f.files}
         r = reps[s]
         _say(f"  slice {s}: freeze {r['k_freeze']} stop {r['outer_iterations']} (oracle {int(fx['k_freeze'])}, "
