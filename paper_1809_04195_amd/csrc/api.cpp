@@ -1420,6 +1420,14 @@ int t2s_stream_run(t2s_plan* plan, int min_done, t2s_stream_status* status, void
             chunk = std::min(chunk, std::min(ce - sl.k % ce, prm.n_outer - sl.k));
         }
         if (nact == 0) break;
+        // once the queue is empty and fewer than half the slots hold a slice, the
+        // XCD-grouped orders (contiguous slot ranges per XCD) would leave some XCDs
+        // without work: the remaining launches deal workgroups round-robin (same
+        // arithmetic; eager launches only, a captured graph keeps its order)
+        bool queued = false;
+        for (size_t i = q.head; i < q.items.size() && !queued; ++i) queued = q.items[i].next < q.items[i].count;
+        const bool drained = !queued && 2 * nact < c.S;
+        c.args.order = (drained && !use_graph) ? (c.order & t2s::kOrderLds2C) : c.order;
         q.slice_outer += (int64_t)nact * chunk;
         for (int i = 0; i < chunk; ++i) {
             if (use_graph) {
@@ -1455,6 +1463,7 @@ int t2s_stream_run(t2s_plan* plan, int min_done, t2s_stream_status* status, void
         }
         if (min_done > 0 && q.done - done0 >= min_done) break;
     }
+    c.args.order = c.order;
     plan->reconstructed = true;
     if (status) {
         long f = 0;
