@@ -585,3 +585,23 @@ def test_two_map_sets_llr_per_set():
     out = O.llr_prox(v, 0.6, (3, 5), 8)
     assert rel(out[0], O.llr_prox(v[0], 0.6, (3, 5), 8)) < 1e-14
     assert rel(out[1], O.llr_prox(v[1], 0.6, (3, 5), 8)) < 1e-14
+
+
+def test_admm_residuals_closed_forms():
+    # r_p = ||alpha - z|| / d, r_d = ||z - z_prev|| / d, d = max(||alpha||, ||z||, floor ||b0||)
+    rng = np.random.default_rng(40)
+    z = crandn(rng, 3, 8, 8)
+    nz = np.linalg.norm(z)
+    rp, rd = O.admm_residuals(z, z, z, 0 * z, 0.1)
+    assert rp == 0.0 and rd == 0.0
+    # alpha = 2 z: d = ||alpha|| = 2 ||z||, r_p = 1/2; z_prev = 0: r_d = ||z|| / (2 ||z||)
+    rp, rd = O.admm_residuals(2 * z, z, 0 * z, 0 * z, 0.1)
+    assert abs(rp - 0.5) < 1e-14 and abs(rd - 0.5) < 1e-14
+    # the scale is the larger of the two norms, whichever it is
+    rp, _ = O.admm_residuals(0.5 * z, z, z, 0 * z, 0.1)
+    assert abs(rp - 0.5 * nz / nz) < 1e-14
+    # a tiny solution: the floor O.RESIDUAL_SCALE_FLOOR ||b0|| takes over as the scale
+    rp, rd = O.admm_residuals(1e-6 * z, 0 * z, 0 * z, 0 * z, 0.1, b0_norm=nz)
+    assert abs(rp - 1e-6 / O.RESIDUAL_SCALE_FLOOR) < 1e-12 and rd == 0.0
+    # all zero, no signal: both residuals 0 (the empty slice stops at its first check)
+    assert O.admm_residuals(0 * z, 0 * z, 0 * z, 0 * z, 0.1) == (0.0, 0.0)
