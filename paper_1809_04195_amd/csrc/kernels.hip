@@ -830,8 +830,16 @@ constexpr int pow2_at_least(int b) { return b <= 1 ? 1 : 2 * pow2_at_least((b + 
 // MODE kLlrFista: x_new = SVT(y - step (A^H A y - b0)), the next momentum point
 // y = x_new + (t_k - 1) / t_(k+1) (x_new - x) into z (Beck & Teboulle's momentum
 // sequence t_0 = 1, t_(k+1) = (1 + sqrt(1 + 4 t_k^2)) / 2, from the iteration counter).
+// At K = 5 the Gram and eigenvector matrices (FP64 complex, 5 x 5 each) take the
+// kernel just past the registers of two waves per SIMD (256 + 27); asking for two
+// waves spills 112 bytes per lane and still runs 22 % faster (10.96 -> 8.56 ms per
+// 512-slice launch at 384^2).  Larger K would spill far more and keep one wave.
+template <int K>
+constexpr int llr_min_waves() { return K == 5 ? 2 : 1; }
+
 template <int K, int B, int MODE>
-__global__ __launch_bounds__(kThreads) void k_llr(ClassArgs a, int s0, int kouter, const float2* __restrict__ inp,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(llr_min_waves<K>())))
+void k_llr(ClassArgs a, int s0, int kouter, const float2* __restrict__ inp,
                                                    float2* __restrict__ outp, float tau, int sy_arg, int sz_arg,
                                                    float step) {
     __shared__ double red[kThreads / 64];
