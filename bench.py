@@ -239,7 +239,7 @@ def main():
     from synth import make_config
 
     t0 = time.perf_counter()
-    d = make_config(4)
+    d = make_config("vol512_384x384_c16_t100_k5")
     cfg, phi = d["cfg"], d["phi"]
     cl = d["classes"][0]
     S, B, K, ncg, P = cl.nslices, args.batch, phi.shape[1], cfg["n_cg"], args.slots
@@ -248,7 +248,7 @@ def main():
     d320 = None
     if not args.no_vol320:
         t1 = time.perf_counter()
-        d320 = make_config(1)      # synthesised before the GPU is initialised (forked workers)
+        d320 = make_config("vol320_256x256_c8_t80_k4")      # synthesised before the GPU is initialised (forked workers)
         log(f"generated {d320['cfg']['name']} in {time.perf_counter() - t1:.1f} s")
 
     # the oracle runs before the GPU is initialised (its workers are forked); its time

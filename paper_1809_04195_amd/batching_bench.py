@@ -24,7 +24,7 @@ def main():
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from synth import make_config
 
-    d = make_config(2)      # synthesised before the GPU is initialised (forked workers)
+    d = make_config("mixed48_192c6_256c8_320x256c12_t80_k4")      # synthesised before the GPU is initialised (forked workers)
     import torch
 
     from . import (T2S_BATCHED, T2S_BATCHED_GRAPH, T2S_PER_SLICE, Plan, t2s_autotune, t2s_get_order,

@@ -68,7 +68,7 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     t0 = time.perf_counter()
-    d = make_config(1, workers=args.gen_workers or None)
+    d = make_config("vol320_256x256_c8_t80_k4", workers=args.gen_workers or None)
     cfg, phi, cl = d["cfg"], d["phi"], d["classes"][0]
     S, K, b, lam = cl.nslices, phi.shape[1], cfg["block"], cfg["lam"]
     log(f"volume {S} x {cl.ny}x{cl.nz} C{cl.ncoils} generated in {time.perf_counter() - t0:.1f} s")

@@ -193,8 +193,8 @@ def run_tolerance(phi, cl, cfg, start, net=None, batch=16, mode=T2S_BATCHED_GRAP
 # Workloads: the training geometry (2D phantoms, its own masks) follows the volume
 # the network is evaluated on; targets are the fixed 100 x 5 schedule's solution.
 WORKLOADS = {
-    "eval320": dict(eval_cfg=3, ny=256, nz=256, C=8, K=4, frac=0.015, chunk=800),
-    "vol512": dict(eval_cfg=4, ny=384, nz=384, C=16, K=5, frac=0.01, chunk=200),
+    "eval320": dict(eval_workload="warmstart_eval320_256x256_c8_t80_k4", ny=256, nz=256, C=8, K=4, frac=0.015, chunk=800),
+    "vol512": dict(eval_workload="vol512_384x384_c16_t100_k5", ny=384, nz=384, C=16, K=5, frac=0.01, chunk=200),
 }
 
 
@@ -232,7 +232,7 @@ def main():
     from synth import CONFIGS, basis, make_config
 
     assert torch.cuda.is_available()
-    ecfg = dict(CONFIGS[wl["eval_cfg"]])
+    ecfg = dict(CONFIGS[wl["eval_workload"]])
     tcfg = dict(ecfg, n_outer=100, n_cg=5, tol=0.0, frac=wl["frac"])      # schedule of the training targets
     phi = basis(ecfg["T"], ecfg["K"])
     K = phi.shape[1]
@@ -269,7 +269,7 @@ def main():
 
     # held-out evaluation volume
     t0 = time.perf_counter()
-    d = make_config(wl["eval_cfg"], max_slices=args.eval_slices or None)
+    d = make_config(wl["eval_workload"], max_slices=args.eval_slices or None)
     cl = d["classes"][0]
     log(f"evaluation volume ({cl.nslices} x {cl.ny}x{cl.nz} C{cl.ncoils}) generated in {time.perf_counter() - t0:.1f} s")
     runs = {}

@@ -44,26 +44,26 @@ import scipy.fft as sfft
 ESP_MS = 6.0
 
 # ---------------------------------------------------------------------------
-# Workload descriptions (shapes and schedules of the five workloads)
+# Workload descriptions (shapes and schedules of the five workloads), by name
 # ---------------------------------------------------------------------------
 
 CONFIGS = {
-    0: dict(name="slice64_c4_t16_k3", classes=[dict(ny=64, nz=64, ncoils=4, nslices=1, nx=1)],
+    "slice64_c4_t16_k3": dict(name="slice64_c4_t16_k3", classes=[dict(ny=64, nz=64, ncoils=4, nslices=1, nx=1)],
             T=16, K=3, frac=0.04, center_frac=None, snr=30.0, dims=2, lam=0.01, rho=0.1, block=8,
             n_outer=20, n_cg=5, tol=0.0, seed=0),
-    1: dict(name="vol320_256x256_c8_t80_k4", classes=[dict(ny=256, nz=256, ncoils=8, nslices=320, nx=320)],
+    "vol320_256x256_c8_t80_k4": dict(name="vol320_256x256_c8_t80_k4", classes=[dict(ny=256, nz=256, ncoils=8, nslices=320, nx=320)],
             T=80, K=4, frac=0.015, center_frac=0.10, snr=30.0, dims=3, lam=0.01, rho=0.1, block=8,
             n_outer=100, n_cg=5, tol=0.0, seed=1),
-    2: dict(name="mixed48_192c6_256c8_320x256c12_t80_k4",
+    "mixed48_192c6_256c8_320x256c12_t80_k4": dict(name="mixed48_192c6_256c8_320x256c12_t80_k4",
             classes=[dict(ny=192, nz=192, ncoils=6, nslices=16, nx=256, seed=2),
                      dict(ny=256, nz=256, ncoils=8, nslices=16, nx=256, seed=3),
                      dict(ny=320, nz=256, ncoils=12, nslices=16, nx=256, seed=4)],
             T=80, K=4, frac=0.015, center_frac=0.10, snr=30.0, dims=3, lam=0.01, rho=0.1, block=8,
             n_outer=100, n_cg=5, tol=0.0, seed=2),
-    3: dict(name="warmstart_eval320_256x256_c8_t80_k4", classes=[dict(ny=256, nz=256, ncoils=8, nslices=320, nx=320)],
+    "warmstart_eval320_256x256_c8_t80_k4": dict(name="warmstart_eval320_256x256_c8_t80_k4", classes=[dict(ny=256, nz=256, ncoils=8, nslices=320, nx=320)],
             T=80, K=4, frac=0.015, center_frac=0.10, snr=30.0, dims=3, lam=0.01, rho=0.1, block=8,
             n_outer=500, n_cg=5, tol=1e-4, seed=11),
-    4: dict(name="vol512_384x384_c16_t100_k5", classes=[dict(ny=384, nz=384, ncoils=16, nslices=512, nx=512)],
+    "vol512_384x384_c16_t100_k5": dict(name="vol512_384x384_c16_t100_k5", classes=[dict(ny=384, nz=384, ncoils=16, nslices=512, nx=512)],
             T=100, K=5, frac=0.01, center_frac=0.10, snr=30.0, dims=3, lam=0.01, rho=0.1, block=8,
             n_outer=500, n_cg=5, tol=1e-4, seed=5),
 }
@@ -390,10 +390,13 @@ def _class_slices(cfg, cl, slices, workers=None):
     return SliceSet(ny, nz, C, masks, sens, ksp, slices)
 
 
-def make_config(cfg_id: int, slices=None, max_slices=None, workers=None):
-    """Generate workload ``cfg_id``.  ``slices`` selects readout positions (single
-    class workloads); ``max_slices`` keeps the first n of each class."""
-    cfg = dict(CONFIGS[cfg_id])
+def make_config(name: str, slices=None, max_slices=None, workers=None):
+    """Generate the workload called ``name`` (a key of CONFIGS).  ``slices`` selects
+    readout positions (single class workloads); ``max_slices`` keeps the first n of
+    each class."""
+    if name not in CONFIGS:
+        raise KeyError(f"unknown workload {name!r}; known: {sorted(CONFIGS)}")
+    cfg = dict(CONFIGS[name])
     phi = basis(cfg["T"], cfg["K"])
     classes = []
     for cl in cfg["classes"]:

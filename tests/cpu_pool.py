@@ -16,9 +16,9 @@ def _admm_job(job):
     return O.admm(ksp, sens, phi, masks, **kw).alpha
 
 
-def _config_job(conn, cfg_id, kw):
+def _config_job(conn, name, kw):
     from synth import make_config
-    conn.send(make_config(cfg_id, **kw))
+    conn.send(make_config(name, **kw))
     conn.close()
 
 
@@ -46,13 +46,13 @@ def admm_many(jobs, procs=16):
             return pool.map(_admm_job, jobs)
 
 
-def make_config_spawned(cfg_id, **kw):
-    """synth.make_config(cfg_id, **kw), run in a fresh (non-daemonic) process, which
+def make_config_spawned(name, **kw):
+    """synth.make_config(name, **kw), run in a fresh (non-daemonic) process, which
     may fork its own synthesis workers."""
     import multiprocessing as mp
     ctx = mp.get_context("spawn")
     recv, send = ctx.Pipe(duplex=False)
-    proc = ctx.Process(target=_config_job, args=(send, cfg_id, kw))
+    proc = ctx.Process(target=_config_job, args=(send, name, kw))
     proc.start()
     send.close()
     try:

@@ -9,7 +9,7 @@ prescribes and stores, in ``tests/golden/oracle_<case>.npz``:
   k_freeze     int                     outer index whose shift was frozen (-1: never)
   n_outer      int                     outer iterations run
   residuals    float64 [n_outer]       max(r_p, r_d) after every outer iteration
-  cfg, cls, slice, g                   workload id, shape class, slice index in
+  cfg, cls, slice, g                   workload name, shape class, slice index in
                                        the class, global slice index of the shifts
 
 Cases (the GPU tests run the whole plan and compare these slices):
@@ -39,16 +39,16 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 
 # (case name, workload, shape class, slice index inside the class)
 CASES = [
-    ("vol512_s200", 4, 0, 200),
-    ("vol512_s330", 4, 0, 330),
-    ("eval320_s120", 3, 0, 120),
-    ("eval320_s200", 3, 0, 200),
-    ("vol320_s0", 1, 0, 0),
-    ("vol320_s160", 1, 0, 160),
-    ("vol320_s250", 1, 0, 250),
-    ("mixed48_c0", 2, 0, 0),
-    ("mixed48_c1", 2, 1, 8),
-    ("mixed48_c2", 2, 2, 15),
+    ("vol512_s200", "vol512_384x384_c16_t100_k5", 0, 200),
+    ("vol512_s330", "vol512_384x384_c16_t100_k5", 0, 330),
+    ("eval320_s120", "warmstart_eval320_256x256_c8_t80_k4", 0, 120),
+    ("eval320_s200", "warmstart_eval320_256x256_c8_t80_k4", 0, 200),
+    ("vol320_s0", "vol320_256x256_c8_t80_k4", 0, 0),
+    ("vol320_s160", "vol320_256x256_c8_t80_k4", 0, 160),
+    ("vol320_s250", "vol320_256x256_c8_t80_k4", 0, 250),
+    ("mixed48_c0", "mixed48_192c6_256c8_320x256c12_t80_k4", 0, 0),
+    ("mixed48_c1", "mixed48_192c6_256c8_320x256c12_t80_k4", 1, 8),
+    ("mixed48_c2", "mixed48_192c6_256c8_320x256c12_t80_k4", 2, 15),
 ]
 
 # Tolerance-mode decision constants of the workloads (freeze window, stall fraction,
@@ -60,16 +60,16 @@ def fixture_path(case):
     return os.path.join(HERE, f"oracle_{case}.npz")
 
 
-def case_inputs(cfg_id, cls, s):
-    """(cfg, phi, masks, sens, ksp, g) of slice s of class cls of workload cfg_id."""
+def case_inputs(workload, cls, s):
+    """(cfg, phi, masks, sens, ksp, g) of slice s of class cls of workload workload."""
     import numpy as np
     from synth import CONFIGS, make_config
-    cfg = CONFIGS[cfg_id]
+    cfg = CONFIGS[workload]
     if len(cfg["classes"]) == 1:
-        d = make_config(cfg_id, slices=[s], workers=1)
+        d = make_config(workload, slices=[s], workers=1)
         g = s
     else:
-        d = make_config(cfg_id, workers=1)
+        d = make_config(workload, workers=1)
         g = sum(c["nslices"] for c in cfg["classes"][:cls]) + s
     cl = d["classes"][cls]
     i = 0 if len(cfg["classes"]) == 1 else s
@@ -78,19 +78,19 @@ def case_inputs(cfg_id, cls, s):
 
 
 def run_case(case):
-    name, cfg_id, cls, s = case
+    name, workload, cls, s = case
     os.environ.update(OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     sys.path.insert(0, ROOT)
     import numpy as np
     from oracle import t2s as O
     t0 = time.perf_counter()
-    cfg, phi, masks, sens, ksp, g = case_inputs(cfg_id, cls, s)
+    cfg, phi, masks, sens, ksp, g = case_inputs(workload, cls, s)
     r = O.admm(ksp, sens, phi, masks, cfg["lam"], cfg["rho"], cfg["block"], cfg["n_outer"], cfg["n_cg"],
                cfg["seed"], g=g, tol=cfg["tol"], freeze_window=FREEZE_WINDOW, freeze_stall=FREEZE_STALL,
                check_every=CHECK_EVERY)
     res = np.array([h["res"] for h in r.history])
     np.savez_compressed(fixture_path(name), alpha=r.alpha.astype(np.complex64),
-                        k_freeze=r.k_freeze, n_outer=r.n_outer, residuals=res, cfg=cfg_id, cls=cls, slice=s, g=g)
+                        k_freeze=r.k_freeze, n_outer=r.n_outer, residuals=res, cfg=workload, cls=cls, slice=s, g=g)
     return name, r.k_freeze, r.n_outer, time.perf_counter() - t0
 
 

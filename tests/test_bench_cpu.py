@@ -22,7 +22,7 @@ def test_cpu_baseline_leg_runs_the_oracle():
     sys.path.insert(0, ROOT)
     import bench
     from synth import make_config
-    d = make_config(0)
+    d = make_config("slice64_c4_t16_k3")
     cfg = dict(d["cfg"])
     out = bench.cpu_baseline(d["classes"][0], d["phi"], cfg, 1, 1)
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "slices/s"

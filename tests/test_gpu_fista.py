@@ -27,9 +27,9 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _cfg0():
+def _slice64():
     from synth import make_config
-    d = make_config(0)
+    d = make_config("slice64_c4_t16_k3")
     return d["cfg"], d["phi"], d["classes"][0]
 
 
@@ -54,8 +54,8 @@ def test_lipschitz_parity_and_empty_slice():
     assert L[2] == 0.0
 
 
-def test_fista_cfg0_parity():
-    cfg, phi, cl = _cfg0()
+def test_fista_slice64_parity():
+    cfg, phi, cl = _slice64()
     n_iter = 20
     _say(f"FISTA parity: 64x64 C4 T16 K3, {n_iter} iterations, shift schedule seed {cfg['seed']}")
     m = cl.masks.astype(bool)
@@ -128,7 +128,7 @@ def test_fista_ragged_and_k5(ny, nz, C, Tn, K):
 
 def test_fista_warm_start_and_continuation():
     _say("FISTA from a set_initial start, then a second call continuing from its result (64x64 C4 K3)")
-    cfg, phi, cl = _cfg0()
+    cfg, phi, cl = _slice64()
     m = cl.masks.astype(bool)
     rng = np.random.default_rng(8)
     b0 = O.adjoint(cl.ksp[0], cl.sens[0], phi, m)
@@ -152,7 +152,7 @@ def test_fista_warm_start_and_continuation():
 
 
 def test_fista_argument_errors():
-    cfg, phi, cl = _cfg0()
+    cfg, phi, cl = _slice64()
     plan = T.Plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=1, masks=cl.masks)], lam=0.01, rho=0.1,
                   seed=0)
     with pytest.raises(T.T2SError):

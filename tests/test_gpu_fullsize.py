@@ -77,7 +77,7 @@ def _compare(tag, got, fx):
 def test_vol320_full_schedule_and_cg_residual_drift():
     import torch
     t0 = time.perf_counter()
-    d = make_config_spawned(1)
+    d = make_config_spawned("vol320_256x256_c8_t80_k4")
     cfg, phi, cl = d["cfg"], d["phi"], d["classes"][0]
     _say(f"320-slice 256x256 C8 T80 K4 volume generated in {time.perf_counter() - t0:.1f} s; "
          f"{cfg['n_outer']} outer x {cfg['n_cg']} CG, batched graph")
@@ -109,7 +109,7 @@ def test_vol320_full_schedule_and_cg_residual_drift():
 
 def test_mixed48_full_schedule_graph_autotuned():
     t0 = time.perf_counter()
-    d = make_config_spawned(2)
+    d = make_config_spawned("mixed48_192c6_256c8_320x256c12_t80_k4")
     cfg, phi, cls = d["cfg"], d["phi"], d["classes"]
     _say(f"mixed 48-slice batch generated in {time.perf_counter() - t0:.1f} s; autotuned, graph replay, "
          f"{cfg['n_outer']} x {cfg['n_cg']}")
@@ -142,7 +142,7 @@ def _check_tolerance_slice(plan, s, fx, tag):
 
 def test_eval320_tolerance_mode():
     t0 = time.perf_counter()
-    d = make_config_spawned(3)
+    d = make_config_spawned("warmstart_eval320_256x256_c8_t80_k4")
     cfg, phi, cl = d["cfg"], d["phi"], d["classes"][0]
     _say(f"held-out 320-slice 256x256 volume generated in {time.perf_counter() - t0:.1f} s; cold start to "
          f"tolerance {cfg['tol']}, batched graph")
@@ -167,7 +167,7 @@ def test_vol512_384x384_c16_k5_tolerance_mode():
     S = 512
     readout = [200, 330]
     t0 = time.perf_counter()
-    d = make_config_spawned(4, slices=readout)
+    d = make_config_spawned("vol512_384x384_c16_t100_k5", slices=readout)
     cfg, phi, cl = d["cfg"], d["phi"], d["classes"][0]
     _say(f"384x384 C16 T100 K5: readout slices {readout} generated in {time.perf_counter() - t0:.1f} s; "
          f"{S}-slice plan to tolerance {cfg['tol']}, batched graph")

@@ -149,15 +149,15 @@ def test_llr_prox(K, b):
     plan.close()
 
 
-def _cfg0():
+def _slice64():
     from synth import make_config
-    d = make_config(0)
+    d = make_config("slice64_c4_t16_k3")
     return d["cfg"], d["phi"], d["classes"][0]
 
 
-def test_admm_cfg0_parity():
+def test_admm_slice64_parity():
     _say("ADMM parity: 64x64 C4 T16 K3, 20 outer x 5 CG, seed 0")
-    cfg, phi, cl = _cfg0()
+    cfg, phi, cl = _slice64()
     plan = _plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=1, masks=cl.masks)],
                  lam=cfg["lam"], rho=cfg["rho"], block=cfg["block"], n_outer=cfg["n_outer"], n_cg=cfg["n_cg"],
                  seed=cfg["seed"])
@@ -236,7 +236,7 @@ def test_multiclass_parity():
 
 def test_warm_start_parity():
     _say("warm start (set_initial) parity, 64x64 C4 K3")
-    cfg, phi, cl = _cfg0()
+    cfg, phi, cl = _slice64()
     rng = np.random.default_rng(2)
     m = cl.masks.astype(bool)
     b0 = O.adjoint(cl.ksp[0], cl.sens[0], phi, m)
@@ -255,7 +255,7 @@ def test_warm_start_parity():
 
 def test_tolerance_mode_replay_parity():
     _say("tolerance mode: GPU decisions replayed by the oracle, 64x64 C4 K3")
-    cfg, phi, cl = _cfg0()
+    cfg, phi, cl = _slice64()
     m = cl.masks.astype(bool)
     plan = _plan(phi, [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=1, masks=cl.masks)],
                  lam=cfg["lam"], rho=cfg["rho"], n_outer=300, n_cg=5, seed=cfg["seed"], tol=1e-4,
@@ -284,7 +284,7 @@ def test_tolerance_mode_replay_parity():
 def test_tolerance_mode_on_a_side_stream_with_device_inputs():
     import torch
     _say("tolerance mode on a non-blocking torch stream, device inputs, vs the default stream")
-    cfg, phi, cl = _cfg0()
+    cfg, phi, cl = _slice64()
     kw = dict(lam=cfg["lam"], rho=cfg["rho"], n_outer=300, n_cg=5, seed=cfg["seed"], tol=1e-4, freeze_window=5,
               freeze_stall=0.05, check_every=5)
     classes = [dict(ny=cl.ny, nz=cl.nz, ncoils=cl.ncoils, nslices=1, masks=cl.masks)]
@@ -310,7 +310,7 @@ def test_tolerance_mode_on_a_side_stream_with_device_inputs():
 
 def test_tolerance_mode_empty_slice_stops_first_check():
     _say("tolerance mode: a slice with no signal next to a normal one")
-    cfg, phi, cl = _cfg0()
+    cfg, phi, cl = _slice64()
     m = cl.masks.astype(bool)
     sens = np.concatenate([cl.sens, cl.sens])
     ksp = np.concatenate([cl.ksp, np.zeros_like(cl.ksp)])

@@ -161,7 +161,7 @@ def test_eval320_streamed_through_64_slots_against_oracle():
     import torch
     from cpu_pool import make_config_spawned
     t0 = time.perf_counter()
-    d = make_config_spawned(3)
+    d = make_config_spawned("warmstart_eval320_256x256_c8_t80_k4")
     cfg, phi, cl = d["cfg"], d["phi"], d["classes"][0]
     _say(f"held-out 320-slice 256x256 volume generated in {time.perf_counter() - t0:.1f} s; streamed through "
          f"64 slots, cold, tolerance {cfg['tol']}")
