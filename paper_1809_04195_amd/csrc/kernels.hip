@@ -274,7 +274,7 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
     for (int i = tid; i < L; i += NT) tw[i] = a.twz[i];
 
     const int r1 = tid / P, t1 = tid - r1 * P;   // mapping 1 (t fastest)
-    const bool on1 = t1 < R2;
+    const bool on1 = R2 == P || t1 < R2;         // every lane when R2 == P (known at compile time)
     const int r3 = tid % RT, t3 = tid / RT;      // mapping 3 (row fastest)
     const bool on3 = t3 < R1;
 
@@ -301,7 +301,10 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
     float2* xr1 = xb + r1 * TB;
     const float2* xr3 = xb + r3 * TB;
     // the next coil's map row is loaded while the current one is transformed (up to 24
-    // values per thread; 32 at 512 points leave no registers for it)
+    // values per thread; 32 at 512 points leave no registers for it), into the same
+    // registers once the current row has been used: a copy "v = next" before the loads
+    // would be merged at the end of the on1 block and wait there for the loads in
+    // flight, before the exchange barrier
     constexpr bool kPrefetch = M == 1 && R1 <= 24;
     const float2* S0 = a.sens + (size_t)s * a.C * M * N + rowoff + t1;
     float2 sn[R1];
@@ -314,17 +317,16 @@ void k_passA(ClassArgs a, int s0, const float2* __restrict__ src,
             float2 v[R1];
             if constexpr (kPrefetch) {
 #pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1) v[n1] = sn[n1];
+                for (int n1 = 0; n1 < R1; ++n1) v[n1] = cmul(sn[n1], pv[0][n1]);
+                __builtin_amdgcn_sched_barrier(0);
                 if (c + 1 < a.C) {
                     const float2* S = S0 + (size_t)(c + 1) * N;
 #pragma unroll
                     for (int n1 = 0; n1 < R1; ++n1) sn[n1] = S[R2 * n1];
                 }
-                // all of the next coil's loads in flight before the first use (the
-                // scheduler would otherwise interleave load / wait / multiply)
+                // all of the next coil's loads issued before the transform (the
+                // scheduler would otherwise interleave load / wait / use)
                 __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1) v[n1] = cmul(v[n1], pv[0][n1]);
             } else {
                 // sum over the map sets of S_(c,m) p_(m,k)
 #pragma unroll
@@ -402,22 +404,25 @@ __global__ __launch_bounds__(colB<L>() * RegGeom<L>::P) void k_passB(ClassArgs a
     float2* xw = xb + w * TB;
 
     float2 F[K][R2];
-    float2 nxt[R1];   // next coefficient's column, loaded while the current one is transformed
+    // coefficient k's column is in col2[k & 1]; the next one loads into the other buffer
+    // while k is transformed.  Two buffers rather than a copy "v = next": where only
+    // some lanes load (R2 < P, e.g. 16 of 24 at 384 points) such a copy is merged at the
+    // end of their block, and the merge waits for the loads in flight, before the
+    // exchange barrier; with alternating buffers the loads stay in flight across it.
+    float2 col2[2][R1];
     if (t < R2) {
 #pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) nxt[n1] = ld_stream<passB_nt<L>()>(&col[tile_row(R2 * n1)]);
+        for (int n1 = 0; n1 < R1; ++n1) col2[0][n1] = ld_stream<passB_nt<L>()>(&col[tile_row(R2 * n1)]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (t < R2) {
-            float2 v[R1];
-#pragma unroll
-            for (int n1 = 0; n1 < R1; ++n1) v[n1] = nxt[n1];
             if (k + 1 < K) {
 #pragma unroll
                 for (int n1 = 0; n1 < R1; ++n1)
-                    nxt[n1] = ld_stream<passB_nt<L>()>(&col[(size_t)(k + 1) * N + tile_row(R2 * n1)]);
+                    col2[(k + 1) & 1][n1] = ld_stream<passB_nt<L>()>(&col[(size_t)(k + 1) * N + tile_row(R2 * n1)]);
             }
+            float2(&v)[R1] = col2[k & 1];
             dft_dir<R1, false>(v);
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) xw[k1 * (R2 + 1) + t] = tw_mul<false>(v[k1], tw, t * k1);
