@@ -27,3 +27,13 @@ def test_cpu_baseline_leg_runs_the_oracle():
     out = bench.cpu_baseline(d["classes"][0], d["phi"], cfg, 1, 1)
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "slices/s"
     assert out["value"] > 0 and "1 of 20" in out["sample"]
+
+
+def test_workloads_are_looked_up_by_name():
+    sys.path.insert(0, ROOT)
+    import pytest
+    from synth import CONFIGS, make_config
+    assert all(k == v["name"] for k, v in CONFIGS.items())
+    for bad in (4, "vol512", ""):
+        with pytest.raises(KeyError):
+            make_config(bad)
