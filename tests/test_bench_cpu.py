@@ -37,3 +37,28 @@ def test_workloads_are_looked_up_by_name():
     for bad in (4, "vol512", ""):
         with pytest.raises(KeyError):
             make_config(bad)
+
+
+def test_committed_bench_line_is_self_consistent():
+    """The committed bench line's derived figures follow from its own measurements:
+    achieved bandwidth = algorithmic bytes per launch / average launch time, frac =
+    achieved / peak, slices/s = slices / seconds per volume; its traffic fields are
+    the counter summary's figures for the same kernel; and the kernel-trace summary
+    of the same workload gives the dominant kernel's average launch time within 2 %."""
+    prof = os.path.join(ROOT, "profiles")
+    b = json.load(open(os.path.join(prof, "bench_vol512_384x384_c16_t100_k5.json")))
+    r = b["roofline"]
+    assert abs(r["achieved"] - r["alg_bytes_per_launch"] / r["avg_launch_ms"] / 1e6) < 1e-3 * r["achieved"]
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    assert b["kernels"][r["kernel"]]["avg_ms"] == r["avg_launch_ms"]
+    assert abs(b["value"] - b["slices_completed"] / b["s_per_volume"]) < 1e-2
+    t = json.load(open(os.path.join(prof, "hbm_traffic_vol512_384x384_c16_t100_k5.json")))
+    tk = t["traffic"][r["kernel"]]
+    assert t["workload"] == b["config"]["workload"]
+    assert abs(r["traffic"] - tk["bytes_per_launch"]) <= 1
+    assert abs(r["traffic_vs_alg"] - tk["ratio_to_alg"]) < 1e-3
+    rows = [ln for ln in open(os.path.join(prof, "kernel_stats_vol512_384x384_c16_t100_k5.md"))
+            if ln.startswith("| `") and "k_passB<384, 5>" in ln]
+    assert len(rows) == 1
+    avg_ms = int(rows[0].split("|")[4]) / 1e6
+    assert abs(avg_ms - r["avg_launch_ms"]) < 0.02 * r["avg_launch_ms"]
